@@ -1,0 +1,182 @@
+"""Plain FP64 CPU oracle for the polyhedral-homotopy hot path (arXiv 2111.14317).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the benchmark's
+CPU-baseline leg; never by the library.  The arithmetic lives in `hom_oracle.c` (plain C99,
+double complex): monomials by repeated multiplication, explicit derivatives (Sec. 5.1), one
+partially pivoted LU for the Euler and Newton directions (Sec. 2.3, Sec. 6), a predictor-corrector
+tracker whose constants come from `TrackParams`, and the implicit-function-theorem gradient.
+
+Parity status of each function (what pins it is in tests/test_oracle_*.py):
+  eval            pinned: central finite differences, 50-digit mpmath, exact values at x = +-1,
+                  branch invariance, J_x = J_z diag(e^{-z}), zeros at binomial roots
+  step            pinned: LAPACK solve, Cramer's rule, closed-form directions of binomial systems
+  track           pinned: closed-form binomial paths, mixed-volume root count, residuals
+  endpoint_grad   pinned: central finite differences of re-solved endpoints
+  residual        pinned: zeros at binomial roots, scale invariance
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hom_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+# path status codes (same meaning as the library's)
+OK, START, RUNNING = 0, 1, 2
+SINGULAR, STEP_MIN, DIVERGED, NONFINITE, POLISH_FAIL, ENDGAME_FAIL, MAX_ITERS = -1, -2, -3, -4, -5, -6, -7
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP over independent points)."""
+    if force or not os.path.exists(_LIB_PATH):
+        os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int, ctypes.c_int64
+        _lib.oracle_eval.argtypes = [i32, P, P, P, P, i64, P, P, i32, P, P, P, i32]
+        _lib.oracle_step.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, i32]
+        _lib.oracle_track.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
+        _lib.oracle_residual.argtypes = [i32, P, P, P, i64, P, P, i32]
+        _lib.oracle_endpoint_grad.argtypes = [i32, P, P, P, P, i64, P, P, P]
+        _lib.oracle_endpoint_grad.restype = i32
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _sys_arrays(sys):
+    return (np.ascontiguousarray(sys.m, np.int32), np.ascontiguousarray(sys.A, np.int8),
+            np.ascontiguousarray(sys.w, np.float64))
+
+
+def default_threads() -> int:
+    return os.cpu_count() or 1
+
+
+def eval(sys, c, z, s, scaled=True, threads=None, with_den=False):
+    """G [P][n][n+2] = [J_z | H_s | H] (rows scaled by e^{-logscale} when `scaled`), logscale
+    [P][n], and optionally den[P][n][n+2] = sum_a |term_a| |C_{a,col}| (the componentwise scale
+    used by the parity metric)."""
+    lib = _load()
+    m, A, w = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    z = np.ascontiguousarray(z, np.complex128).reshape(-1, sys.n)
+    s = np.ascontiguousarray(s, np.float64).reshape(-1)
+    P, n = z.shape[0], sys.n
+    G = np.zeros((P, n, n + 2), np.complex128)
+    L = np.zeros((P, n), np.float64)
+    den = np.zeros((P, n, n + 2), np.float64) if with_den else None
+    lib.oracle_eval(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), int(scaled),
+                    _ptr(G), _ptr(L), _ptr(den), threads or default_threads())
+    return (G, L, den) if with_den else (G, L)
+
+
+def step(sys, c, z, s, threads=None):
+    """Euler and Newton directions dE = -J_z^{-1} H_s, dN = -J_z^{-1} H at every point, status
+    (0, or -1 when a pivot is exactly zero) and the pivot ratio min|u_jj| / max|u_jj|."""
+    lib = _load()
+    m, A, w = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    z = np.ascontiguousarray(z, np.complex128).reshape(-1, sys.n)
+    s = np.ascontiguousarray(s, np.float64).reshape(-1)
+    P, n = z.shape[0], sys.n
+    dE = np.zeros((P, n), np.complex128)
+    dN = np.zeros((P, n), np.complex128)
+    st = np.zeros(P, np.int32)
+    ratio = np.zeros(P, np.float64)
+    lib.oracle_step(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(dE),
+                    _ptr(dN), _ptr(st), _ptr(ratio), threads or default_threads())
+    return dE, dN, st, ratio
+
+
+@dataclasses.dataclass
+class TrackParams:
+    """Tracker constants (the paper fixes none; these are this implementation's choices)."""
+
+    ds0: float = 0.05
+    ds_max: float = 0.5
+    ds_min: float = 1e-10
+    tol_polish: float = 1e-12
+    tol_track: float = 1e-8
+    tol_end: float = 1e-14
+    res_tol: float = 1e-10
+    div_re: float = 40.0
+    sing_ratio: float = 1e-14
+    max_polish: int = 5
+    max_newton: int = 3
+    max_end: int = 8
+    max_steps: int = 100000
+    max_iters: int = 1000000
+
+    def arrays(self):
+        d = np.array([self.ds0, self.ds_max, self.ds_min, self.tol_polish, self.tol_track,
+                      self.tol_end, self.res_tol, self.div_re, self.sing_ratio], np.float64)
+        i = np.array([self.max_polish, self.max_newton, self.max_end, self.max_steps,
+                      self.max_iters], np.int32)
+        return d, i
+
+
+def track(sys, c, z0, s0, params: TrackParams | None = None, status=None, ds=None, threads=None):
+    """Track every path from (z0, s0) to s = 0.  Returns (z, s, ds, status, counters[P][4] =
+    accepted steps, rejected steps, corrector iterations, eval+solves)."""
+    lib = _load()
+    params = params or TrackParams()
+    m, A, w = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    z = np.array(z0, np.complex128).reshape(-1, sys.n)
+    P = z.shape[0]
+    s = np.array(np.broadcast_to(np.asarray(s0, np.float64), (P,)))
+    ds = np.zeros(P, np.float64) if ds is None else np.array(ds, np.float64)
+    st = np.full(P, START, np.int32) if status is None else np.array(status, np.int32)
+    cnt = np.zeros((P, 4), np.int32)
+    d, i = params.arrays()
+    lib.oracle_track(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(ds),
+                     _ptr(d), _ptr(i), _ptr(st), _ptr(cnt), threads or default_threads())
+    return z, s, ds, st, cnt
+
+
+def residual(sys, c, z, threads=None):
+    """Relative backward error r(x) = max_k |f_k(x)| / sum_a |c_{k,a} x^a| at t = 1."""
+    lib = _load()
+    m, A, _ = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    z = np.ascontiguousarray(z, np.complex128).reshape(-1, sys.n)
+    out = np.zeros(z.shape[0], np.float64)
+    lib.oracle_residual(sys.n, _ptr(m), _ptr(A), _ptr(c), z.shape[0], _ptr(z), _ptr(out),
+                        threads or default_threads())
+    return out
+
+
+def endpoint_grad(sys, c, z_end, grad_x):
+    """grad_c [M] (PyTorch convention dL/dRe c + i dL/dIm c) of a loss on the endpoints x = e^z,
+    given grad_x = dL/dRe x + i dL/dIm x.  Returns (grad_c, number of singular paths skipped)."""
+    lib = _load()
+    m, A, w = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    z = np.ascontiguousarray(z_end, np.complex128).reshape(-1, sys.n)
+    g = np.ascontiguousarray(grad_x, np.complex128).reshape(-1, sys.n)
+    out = np.zeros(sys.M, np.complex128)
+    ns = lib.oracle_endpoint_grad(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), z.shape[0], _ptr(z),
+                                  _ptr(g), _ptr(out))
+    return out, int(ns)

@@ -1,0 +1,466 @@
+/*
+ * Plain FP64 CPU oracle for the polyhedral-homotopy hot path (arXiv 2111.14317).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is checked against.  It
+ * is used by the test suite, by the smoke check and by the benchmark's CPU-baseline leg, and by
+ * nothing else; it shares no code with the GPU path.
+ *
+ * It follows the definitions directly, with no blocking or reordering:
+ *   - eval : h_k(x,t) = sum_a c_{k,a} x^a t^{w_k(a)} (Sec. 2, eq. (1)) with x = e^z, t = e^s
+ *            (eq. (2)).  Monomials x^a are built by repeated multiplication (x_j^{-1} for
+ *            negative exponents).  The partials in log coordinates are
+ *              dh_k/dz_j = sum_a a_j c_{k,a} x^a t^{w(a)}   and   dh_k/ds = sum_a w(a) c_{k,a} x^a t^{w(a)}
+ *            (Sec. 5.1, the Hadamard-product form of the derivative and the extended row
+ *            [D_z h_k, D_tau h_k, h_k]).  Output row k is [J_z | H_s | H] in that column order.
+ *   - solve: the Euler direction dE solves J_z dE = -H_s (Davidenko equation, Sec. 2.3) and the
+ *            Newton direction dN solves J_z dN = -H (Sec. 2.3).  Both come from one LU with partial
+ *            pivoting of the augmented matrix [J_z | H_s | H] (the unified system of Sec. 6, in
+ *            its affine form).
+ *   - track: a predictor-corrector loop over s in [s0, 0] that uses dE as Euler predictor and dN
+ *            as Newton corrector (Sec. 2.3); the paper gives no step control, so the constants
+ *            and rules are taken from the parameter struct below.
+ *   - grad : gradient of a real loss on the endpoints with respect to the coefficients, through
+ *            the implicit function theorem (the same argument as the Davidenko equation,
+ *            Sec. 2.3): J_x^H nu = -g, grad c_{k,a} = sum_paths nu_k conj(x^a).
+ *
+ * Row scaling.  With `scaled` set, every row k is multiplied by e^{-M_k}, where M_k is the
+ * largest log-magnitude max_a (<a, Re z> + w(a) s) of a monomial of equation k (without c), so
+ * that t^w factors far below the FP64 range do not vanish and x^a far above it does not
+ * overflow.  The term is then formed in polar form, c * (x/|x|)^a * exp(<a, Re z> + s w - M_k),
+ * with the unit-modulus phase factor still built by repeated multiplication.  Directions dE and
+ * dN are invariant under this row scaling.  Without `scaled` (M_k = 0) the term is literally
+ * c * x^a * t^w with x^a and integer powers of t by repeated multiplication.
+ *
+ * Complex numbers are C99 `double complex`, stored interleaved (re, im) like complex128.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define OR_NMAX 32
+
+/* ---------------------------------------------------------------------------------------- */
+/* monomials                                                                                */
+/* ---------------------------------------------------------------------------------------- */
+
+/* x^a by repeated multiplication */
+static cplx monomial(int n, const cplx *x, const cplx *xinv, const int8_t *a) {
+    cplx r = 1.0;
+    for (int j = 0; j < n; j++) {
+        int e = a[j];
+        for (int q = 0; q < e; q++) r *= x[j];
+        for (int q = 0; q < -e; q++) r *= xinv[j];
+    }
+    return r;
+}
+
+/* t^w: repeated multiplication for integer w, exp(s w) otherwise */
+static double lift_power(double s, double w) {
+    if (w == floor(w) && w >= 0 && w <= 4096) {
+        double t = exp(s), r = 1.0;
+        for (int q = 0; q < (int)w; q++) r *= t;
+        return r;
+    }
+    return exp(s * w);
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* eval                                                                                      */
+/* ---------------------------------------------------------------------------------------- */
+
+/* One point.  G: n x (n+2) row-major; logscale: n (0 when unscaled); den (optional):
+ * n x (n+2), den[k][col] = sum_a |term_a| * |C_a,col| with C_a = (a_1..a_n, w(a), 1). */
+static void eval_point(int n, const int32_t *m, const int8_t *A, const double *w, const cplx *c,
+                       const cplx *z, double s, int scaled, cplx *G, double *logscale,
+                       double *den) {
+    cplx x[OR_NMAX], xinv[OR_NMAX], u[OR_NMAX], uinv[OR_NMAX];
+    for (int j = 0; j < n; j++) {
+        x[j] = cexp(z[j]);
+        xinv[j] = 1.0 / x[j];
+        u[j] = cexp(I * cimag(z[j])); /* x_j / |x_j| */
+        uinv[j] = conj(u[j]);
+    }
+    int off = 0;
+    for (int k = 0; k < n; k++) {
+        const int mk = m[k];
+        double Mk = 0.0;
+        if (scaled) {
+            Mk = -INFINITY;
+            for (int i = off; i < off + mk; i++) {
+                double e = w[i] * s;
+                for (int j = 0; j < n; j++) e += (double)A[(size_t)i * n + j] * creal(z[j]);
+                if (e > Mk) Mk = e;
+            }
+        }
+        cplx *row = G + (size_t)k * (n + 2);
+        double *drow = den ? den + (size_t)k * (n + 2) : NULL;
+        for (int col = 0; col < n + 2; col++) {
+            row[col] = 0.0;
+            if (drow) drow[col] = 0.0;
+        }
+        for (int i = off; i < off + mk; i++) {
+            const int8_t *a = A + (size_t)i * n;
+            cplx term;
+            if (scaled) {
+                /* polar form: phase by repeated multiplication of unit-modulus x_j/|x_j|,
+                 * magnitude |x^a t^w| e^{-M_k} = exp(<a, Re z> + s w - M_k) */
+                double lm = s * w[i] - Mk;
+                for (int j = 0; j < n; j++) lm += (double)a[j] * creal(z[j]);
+                term = c[i] * monomial(n, u, uinv, a) * exp(lm);
+            } else {
+                term = c[i] * monomial(n, x, xinv, a) * lift_power(s, w[i]);
+            }
+            for (int j = 0; j < n; j++) row[j] += (double)a[j] * term;
+            row[n] += w[i] * term;
+            row[n + 1] += term;
+            if (drow) {
+                double at = cabs(term);
+                for (int j = 0; j < n; j++) drow[j] += fabs((double)a[j]) * at;
+                drow[n] += fabs(w[i]) * at;
+                drow[n + 1] += at;
+            }
+        }
+        if (logscale) logscale[k] = Mk;
+        off += mk;
+    }
+}
+
+void oracle_eval(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                 int64_t P, const double *z, const double *s, int scaled, double *G,
+                 double *logscale, double *den, int threads) {
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++) {
+        eval_point(n, m, A, w, (const cplx *)c, (const cplx *)z + p * n, s[p], scaled,
+                   (cplx *)G + p * n * (n + 2), logscale ? logscale + p * n : NULL,
+                   den ? den + p * n * (n + 2) : NULL);
+    }
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* solve                                                                                     */
+/* ---------------------------------------------------------------------------------------- */
+
+/* LU with partial pivoting (largest modulus, ties to the lowest row) of the n x n block of the
+ * augmented n x (n+nrhs) matrix Gw (row stride ld), applied to the nrhs right-hand columns,
+ * then back substitution.  X[r][j] (r-th rhs, j-th unknown) = -(J^{-1} rhs_r)_j.
+ * Returns 0, or 1 if a pivot is exactly zero.  *ratio = min |pivot| / max |pivot|. */
+static int lu_solve(int n, int nrhs, cplx *Gw, int ld, cplx *X, double *ratio) {
+    double pmin = INFINITY, pmax = 0.0;
+    for (int j = 0; j < n; j++) {
+        int piv = j;
+        double best = -1.0;
+        for (int r = j; r < n; r++) {
+            cplx v = Gw[r * ld + j];
+            double mag = creal(v) * creal(v) + cimag(v) * cimag(v);
+            if (mag > best) {
+                best = mag;
+                piv = r;
+            }
+        }
+        if (!(best > 0.0)) {
+            if (ratio) *ratio = 0.0;
+            return 1;
+        }
+        if (piv != j)
+            for (int col = 0; col < n + nrhs; col++) {
+                cplx t = Gw[j * ld + col];
+                Gw[j * ld + col] = Gw[piv * ld + col];
+                Gw[piv * ld + col] = t;
+            }
+        double pm = sqrt(best);
+        if (pm < pmin) pmin = pm;
+        if (pm > pmax) pmax = pm;
+        cplx inv = 1.0 / Gw[j * ld + j];
+        for (int r = j + 1; r < n; r++) {
+            cplx l = Gw[r * ld + j] * inv;
+            for (int col = j + 1; col < n + nrhs; col++) Gw[r * ld + col] -= l * Gw[j * ld + col];
+            Gw[r * ld + j] = 0.0;
+        }
+    }
+    for (int q = 0; q < nrhs; q++) {
+        for (int j = n - 1; j >= 0; j--) {
+            cplx acc = Gw[j * ld + n + q];
+            for (int col = j + 1; col < n; col++) acc -= Gw[j * ld + col] * X[q * n + col];
+            X[q * n + j] = acc / Gw[j * ld + j];
+        }
+        for (int j = 0; j < n; j++) X[q * n + j] = -X[q * n + j];
+    }
+    if (ratio) *ratio = pmin / pmax;
+    return 0;
+}
+
+/* one eval + consolidated 2-rhs solve at (z, s). */
+static int step_point(int n, const int32_t *m, const int8_t *A, const double *w, const cplx *c,
+                      const cplx *z, double s, cplx *dE, cplx *dN, double *ratio, double *resid) {
+    cplx G[OR_NMAX * (OR_NMAX + 2)];
+    double den[OR_NMAX * (OR_NMAX + 2)];
+    eval_point(n, m, A, w, c, z, s, 1, G, NULL, den);
+    if (resid) { /* relative backward error max_k |h_k| / sum_a |term_a| */
+        double r = 0.0;
+        for (int k = 0; k < n; k++) {
+            double v = cabs(G[k * (n + 2) + n + 1]) / den[k * (n + 2) + n + 1];
+            if (!(v <= r)) r = v;
+        }
+        *resid = r;
+    }
+    cplx X[2 * OR_NMAX];
+    int st = lu_solve(n, 2, G, n + 2, X, ratio);
+    for (int j = 0; j < n; j++) {
+        dE[j] = st ? NAN : X[j];
+        dN[j] = st ? NAN : X[n + j];
+    }
+    return st;
+}
+
+void oracle_step(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                 int64_t P, const double *z, const double *s, double *dE, double *dN,
+                 int32_t *status, double *ratio, int threads) {
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++) {
+        double r;
+        int st = step_point(n, m, A, w, (const cplx *)c, (const cplx *)z + p * n, s[p],
+                            (cplx *)dE + p * n, (cplx *)dN + p * n, &r, NULL);
+        status[p] = st ? -1 : 0;
+        if (ratio) ratio[p] = r;
+    }
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* track                                                                                     */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Tracker constants.  Field for field the same meaning as the GPU library's parameters. */
+typedef struct {
+    double ds0, ds_max, ds_min;
+    double tol_polish;  /* start-point Newton: stop when ||dN||_inf <= tol_polish */
+    double tol_track;   /* corrector converged when ||dN||_inf <= tol_track */
+    double tol_end;     /* endgame: stop when ||dN||_inf <= tol_end (1 + ||z||_inf) */
+    double res_tol;     /* endpoint accepted when the relative residual <= res_tol */
+    double div_re;      /* |Re z_j| > div_re => diverged */
+    double sing_ratio;  /* min/max |pivot| below this => singular */
+    int max_polish, max_newton, max_end, max_steps, max_iters;
+} or_params;
+
+enum { OR_OK = 0, OR_START = 1, OR_RUNNING = 2, OR_SINGULAR = -1, OR_STEP_MIN = -2,
+       OR_DIVERGED = -3, OR_NONFINITE = -4, OR_POLISH_FAIL = -5, OR_ENDGAME_FAIL = -6,
+       OR_MAX_ITERS = -7 };
+enum { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
+
+static double norm_inf(int n, const cplx *v) {
+    double r = 0.0;
+    for (int j = 0; j < n; j++) {
+        double a = cabs(v[j]);
+        if (!(a <= r)) r = a; /* propagates NaN */
+    }
+    return r;
+}
+
+/* Track one path.  z, s, ds in/out; status in/out (OR_START: polish first, OR_RUNNING: resume
+ * at an accepted point with step ds); counters: steps, rejects, corrector iterations, evals. */
+static void track_path(int n, const int32_t *m, const int8_t *A, const double *w, const cplx *c,
+                       const or_params *pr, cplx *z, double *s_io, double *ds_io, int32_t *status,
+                       int32_t *cnt) {
+    if (*status != OR_START && *status != OR_RUNNING) return;
+    cplx za[OR_NMAX], dEa[OR_NMAX], dE[OR_NMAX], dN[OR_NMAX];
+    double s = *s_io, sa = s, ds = *ds_io, nrm_prev = 0.0;
+    int phase = (*status == OR_START) ? PH_POLISH : PH_RESUME;
+    if (*status == OR_START) ds = pr->ds0;
+    int k = 0, steps_here = 0;
+    for (int j = 0; j < n; j++) za[j] = z[j];
+    for (int it = 0;; it++) {
+        if (it >= pr->max_iters) { *status = OR_MAX_ITERS; break; }
+        double ratio, resid;
+        int sing = step_point(n, m, A, w, c, z, s, dE, dN, &ratio, &resid);
+        cnt[3]++;
+        double nrm = norm_inf(n, dN);
+        if (sing || ratio < pr->sing_ratio) {
+            if (phase == PH_TRACK) goto reject; /* step back and shrink */
+            *status = OR_SINGULAR;
+            break;
+        }
+        if (!isfinite(nrm) || !isfinite(norm_inf(n, dE))) {
+            if (phase == PH_TRACK) goto reject;
+            *status = OR_NONFINITE;
+            break;
+        }
+        if (phase == PH_POLISH) {
+            for (int j = 0; j < n; j++) z[j] += dN[j];
+            k++;
+            cnt[2]++;
+            if (nrm <= pr->tol_polish) {
+                /* on the path: accept (z, s) with the Euler direction just computed */
+                phase = PH_RESUME;
+                k = 0;
+                continue; /* re-evaluate at the polished point before predicting */
+            }
+            if (k >= pr->max_polish) { *status = OR_POLISH_FAIL; break; }
+            continue;
+        }
+        if (phase == PH_RESUME) {
+            /* (z, s) is an accepted point: keep it and predict with its Euler direction */
+            for (int j = 0; j < n; j++) { za[j] = z[j]; dEa[j] = dE[j]; }
+            sa = s;
+            if (sa >= 0.0) { phase = PH_END; k = 0; goto endgame; }
+            if (steps_here >= pr->max_steps) { *status = OR_RUNNING; break; }
+            goto predict;
+        }
+        if (phase == PH_END) goto endgame;
+
+        /* PH_TRACK: corrector */
+        if (nrm <= pr->tol_track) {
+            /* accept the evaluated point */
+            for (int j = 0; j < n; j++) { za[j] = z[j]; dEa[j] = dE[j]; }
+            sa = s;
+            cnt[0]++;
+            steps_here++;
+            if (k <= 1) ds = fmin(2.0 * ds, pr->ds_max);
+            if (sa >= 0.0) { phase = PH_END; k = 0; goto endgame; }
+            if (steps_here >= pr->max_steps) { *status = OR_RUNNING; break; }
+            goto predict;
+        }
+        if (k < pr->max_newton && (k == 0 || nrm <= 0.5 * nrm_prev)) {
+            for (int j = 0; j < n; j++) z[j] += dN[j];
+            k++;
+            cnt[2]++;
+            nrm_prev = nrm;
+            int div = 0;
+            for (int j = 0; j < n; j++) div |= fabs(creal(z[j])) > pr->div_re;
+            if (div) { *status = OR_DIVERGED; break; }
+            continue;
+        }
+    reject:
+        cnt[1]++;
+        ds *= 0.5;
+        if (ds < pr->ds_min) { *status = OR_STEP_MIN; break; }
+        for (int j = 0; j < n; j++) z[j] = za[j];
+        s = sa;
+    predict: {
+        double h = fmin(ds, -sa);
+        for (int j = 0; j < n; j++) z[j] = za[j] + h * dEa[j];
+        s = (h == -sa) ? 0.0 : sa + h;
+        k = 0;
+        phase = PH_TRACK;
+        continue;
+    }
+    endgame:
+        /* s = 0: Newton until the step is tiny or stops contracting */
+        for (int j = 0; j < n; j++) z[j] += dN[j];
+        cnt[2]++;
+        k++;
+        if (nrm <= pr->tol_end * (1.0 + norm_inf(n, z)) || k >= pr->max_end ||
+            (k >= 3 && nrm > 0.5 * nrm_prev)) {
+            *status = (resid <= pr->res_tol) ? OR_OK : OR_ENDGAME_FAIL;
+            break;
+        }
+        nrm_prev = nrm;
+        continue;
+    }
+    *s_io = s;
+    *ds_io = ds;
+}
+
+void oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                  int64_t P, double *z, double *s, double *ds, const double *dparams,
+                  const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {
+    or_params pr;
+    pr.ds0 = dparams[0];
+    pr.ds_max = dparams[1];
+    pr.ds_min = dparams[2];
+    pr.tol_polish = dparams[3];
+    pr.tol_track = dparams[4];
+    pr.tol_end = dparams[5];
+    pr.res_tol = dparams[6];
+    pr.div_re = dparams[7];
+    pr.sing_ratio = dparams[8];
+    pr.max_polish = iparams[0];
+    pr.max_newton = iparams[1];
+    pr.max_end = iparams[2];
+    pr.max_steps = iparams[3];
+    pr.max_iters = iparams[4];
+#pragma omp parallel for schedule(dynamic, 16) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++)
+        track_path(n, m, A, w, (const cplx *)c, &pr, (cplx *)z + p * n, s + p, ds + p,
+                   status + p, counters + 4 * p);
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* residual at t = 1 and endpoint gradient                                                   */
+/* ---------------------------------------------------------------------------------------- */
+
+/* relative backward error r(x) = max_k |f_k(x)| / sum_a |c_{k,a} x^a| at t = 1 */
+void oracle_residual(int n, const int32_t *m, const int8_t *A, const double *c, int64_t P,
+                     const double *z, double *out, int threads) {
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++) {
+        const cplx *zp = (const cplx *)z + p * n;
+        cplx x[OR_NMAX], xinv[OR_NMAX];
+        for (int j = 0; j < n; j++) {
+            x[j] = cexp(zp[j]);
+            xinv[j] = 1.0 / x[j];
+        }
+        double r = 0.0;
+        int off = 0;
+        for (int k = 0; k < n; k++) {
+            cplx f = 0.0;
+            double a = 0.0;
+            for (int i = off; i < off + m[k]; i++) {
+                cplx t = ((const cplx *)c)[i] * monomial(n, x, xinv, A + (size_t)i * n);
+                f += t;
+                a += cabs(t);
+            }
+            double v = cabs(f) / a;
+            if (!(v <= r)) r = v;
+            off += m[k];
+        }
+        out[p] = r;
+    }
+}
+
+/* grad_c (M complex) of L(x*) with upstream g = dL/dRe x + i dL/dIm x at the endpoints.
+ * Per path: J_x^H nu = -g with J_x = J_z diag(e^{-z}), i.e. J_z^H nu = -conj(x) . g; then
+ * grad c_{k,a} += nu_k conj(x^a).  Paths are summed in index order.  Returns the number of
+ * paths whose Jacobian was singular (they are skipped). */
+int oracle_endpoint_grad(int n, const int32_t *m, const int8_t *A, const double *w,
+                         const double *c, int64_t P, const double *z_end, const double *grad_x,
+                         double *grad_c) {
+    int M = 0;
+    for (int k = 0; k < n; k++) M += m[k];
+    cplx *gc = (cplx *)grad_c;
+    for (int i = 0; i < M; i++) gc[i] = 0.0;
+    int nsing = 0;
+    for (int64_t p = 0; p < P; p++) {
+        const cplx *zp = (const cplx *)z_end + p * n;
+        const cplx *gp = (const cplx *)grad_x + p * n;
+        cplx G[OR_NMAX * (OR_NMAX + 2)];
+        double Ms[OR_NMAX];
+        eval_point(n, m, A, w, (const cplx *)c, zp, 0.0, 1, G, Ms, NULL);
+        /* scaled rows: Js = diag(e^{-M}) J_z, so Js^H mu = -conj(x).g with nu = e^{-M} mu */
+        cplx H[OR_NMAX * (OR_NMAX + 1)];
+        for (int r = 0; r < n; r++) {
+            for (int col = 0; col < n; col++) H[r * (n + 1) + col] = conj(G[col * (n + 2) + r]);
+            H[r * (n + 1) + n] = conj(cexp(zp[r])) * gp[r];
+        }
+        cplx mu[OR_NMAX];
+        if (lu_solve(n, 1, H, n + 1, mu, NULL)) { /* mu = -Js^{-H} (conj(x).g) */
+            nsing++;
+            continue;
+        }
+        cplx x[OR_NMAX], xinv[OR_NMAX];
+        for (int j = 0; j < n; j++) {
+            x[j] = cexp(zp[j]);
+            xinv[j] = 1.0 / x[j];
+        }
+        int off = 0;
+        for (int k = 0; k < n; k++) {
+            cplx nu = mu[k] * exp(-Ms[k]);
+            for (int i = off; i < off + m[k]; i++)
+                gc[i] += nu * conj(monomial(n, x, xinv, A + (size_t)i * n));
+            off += m[k];
+        }
+    }
+    return nsing;
+}
