@@ -1,0 +1,186 @@
+"""Benchmark: eval + consolidated Euler/Newton solves per second while tracking paths.
+
+Workload (one step = one full pass of the hot path): a random n = 10 Laurent system with 12
+monomials per equation (exponents uniform in [-3, 3], unit-circle coefficients) and a planted
+mixed cell (lifting 0 on one pair per equation, U{1..63} elsewhere); 65536 paths tracked from
+s = -32 to s = 0 with the persistent predictor-corrector kernel, Euler predictor and Newton
+corrector from one consolidated LU per evaluation, FP64 endgame.  Both forms run: the plain
+FP64 form and the mixed form (FP32 exponentials, contraction and LU).  `value` is the mixed
+form's rate; a form's number counts only when >= 99.9% of its paths end OK (residual <= 1e-10).
+
+Timing: W untimed warmup steps, then K steps back to back, each on its own pre-staged copy of
+the start state (inputs resident in HBM), bracketed by torch.cuda.synchronize().  Kernel
+durations for the roofline come from hipEvents the library records around its own launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "eval+Euler/Newton solves/sec (n=10, 64K paths), mixed vs FP64 at 1e-10 resid"
+UNIT = "eval+solve/s"
+N_EQ, M_EQ = 10, 12
+# algorithmic work of one eval + 2-rhs solve at n = 10, 12 monomials per equation (FMA = 2 flops)
+#   A1 exponent sums  : M (2n + 1) FMA             = 120 * 21 * 2      = 5040
+#   A2 c * exp(u - M) : 3 real mults per monomial  = 120 * 6           =  720   (+3 transcendentals)
+#   A3 contraction    : M ((n + 1) complex FMA by a real + 1 complex add) = 120 * (11*4 + 2) = 5520
+#   A5 LU, 2 rhs      : sum_j (n-1-j)(6 + 8 (n+1-j)) + 10 reciprocals (8) + 2 back-subs (45*8 + 10*6)
+#                     = 3270 + 80 + 840 = 4190
+FLOPS_PER_UNIT = 5040 + 720 + 5520 + 4190
+FP64_SHARE = 5040  # the exponent sums stay FP64 in the mixed form
+PEAK_FP64 = 78.6e12
+PEAK_FP32 = 157.3e12
+
+
+def _peak_mixed():
+    # time lower bound: FP64 part at the FP64 peak, the rest at the FP32 peak
+    t = FP64_SHARE / PEAK_FP64 + (FLOPS_PER_UNIT - FP64_SHARE) / PEAK_FP32
+    return FLOPS_PER_UNIT / t
+
+
+def _workload(P):
+    import workloads as W
+    csys, cell, z0 = W.planted_config("c2", P=P)
+    return csys, z0
+
+
+def run_form(hom, torch, h, csys, z0, precision, steps, warmup):
+    """Returns dict with rate, ms/step, ok fraction, mean evals/path and kernel timings."""
+    dev = "cuda"
+    P = z0.shape[0]
+    c = torch.tensor(csys.c, dtype=torch.complex128, device=dev)
+    z_init = torch.tensor(z0, dtype=torch.complex128, device=dev)
+    params = hom.default_params(precision)
+    total = warmup + steps
+    states = []
+    for _ in range(total):
+        states.append(hom.TrackState(
+            z_init.clone(), torch.full((P,), -32.0, dtype=torch.float64, device=dev),
+            torch.zeros(P, dtype=torch.float64, device=dev),
+            torch.full((P,), hom.PATH_START, dtype=torch.int32, device=dev),
+            torch.zeros((P, 4), dtype=torch.int32, device=dev)))
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        hom.track(h, c, None, None, params, state=states[i])
+    torch.cuda.synchronize()
+    hom.profile_read()  # drop anything recorded so far
+    hom.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, total):
+        hom.track(h, c, None, None, params, state=states[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hom.set_profiling(False)
+    prof = hom.profile_read()
+    evals = 0
+    ok = []
+    evals_per_path = []
+    for i in range(warmup, total):
+        cnt = states[i].counters.cpu()
+        evals += int(cnt[:, 3].sum())
+        st = states[i].status.cpu()
+        ok.append(float((st == hom.PATH_OK).float().mean()))
+        evals_per_path.append(float(cnt[:, 3].float().mean()))
+    sec = t1 - t0
+    kern, units = {}, {}
+    for name, ms, u in prof:
+        kern.setdefault(name, []).append(ms)
+        units.setdefault(name, []).append(u)
+    return dict(rate=evals / sec, ms_per_step=1e3 * sec / steps, ok_frac=min(ok),
+                evals_per_path=sum(evals_per_path) / len(evals_per_path),
+                evals_per_step=evals / steps, kernels={k: sum(v) / len(v) for k, v in kern.items()},
+                units={k: sum(v) / len(v) for k, v in units.items()},
+                launches={k: len(v) for k, v in kern.items()}, paths_per_s=P * steps / sec)
+
+
+def cpu_baseline(csys, z0, target_s=15.0):
+    """The oracle (unchanged) tracking a bounded sample of the same paths on the host cores."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    n0 = 256
+    t = time.perf_counter()
+    _, _, _, _, cnt = oracle.track(csys, csys.c, z0[:n0], -32.0, threads=threads)
+    dt = time.perf_counter() - t
+    n1 = int(min(len(z0), max(n0, n0 * target_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    _, _, _, st, cnt = oracle.track(csys, csys.c, z0[:n1], -32.0, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": float(cnt[:, 3].sum()) / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"first {n1} of the {len(z0)} paths, tracked s=-32..0 in FP64 "
+                      f"({dt:.1f} s, {float(np.mean(st == 0)):.4f} ok)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--paths", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}); paths shard across GPUs with no exchange, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2111_14317_amd as hom
+    csys, z0 = _workload(args.paths)
+    h = hom.System.from_workload(csys)
+    res = {}
+    for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
+        res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup)
+        print(f"# {name}: {res[name]['rate']:.4e} {UNIT}, {res[name]['ms_per_step']:.2f} ms/step, "
+              f"ok {res[name]['ok_frac']:.5f}, {res[name]['evals_per_path']:.1f} evals/path, "
+              f"kernels {res[name]['kernels']}", file=sys.stderr, flush=True)
+    mixed = res["mixed"]
+    dom = f"k_track<{N_EQ},mixed>"
+    roof = None
+    if dom in mixed["kernels"]:
+        dom_ms, dom_units = mixed["kernels"][dom], mixed["units"][dom]
+        achieved = dom_units * FLOPS_PER_UNIT / (dom_ms * 1e-3)
+        peak = _peak_mixed()
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": dom, "kernel_ms": dom_ms,
+                "kernel_units": dom_units, "flops_per_unit": FLOPS_PER_UNIT}
+    f64 = res["fp64"]
+    f64_dom = f"k_track<{N_EQ},fp64>"
+    f64_frac = None
+    if f64_dom in f64["kernels"]:
+        f64_frac = f64["units"][f64_dom] * FLOPS_PER_UNIT / (f64["kernels"][f64_dom] * 1e-3) / PEAK_FP64
+    out = {
+        "metric": METRIC, "value": mixed["rate"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"track {args.paths} planted-cell paths of a random n=10 Laurent "
+                               "system (12 monomials/eq, exponents U[-3,3], unit-circle coeffs, "
+                               "lifting {0,0,U{1..63}}) from s=-32 to 0, FP64 endgame",
+                   "paths": args.paths, "n": N_EQ, "monomials_per_eq": M_EQ},
+        "fp64": {"value": res["fp64"]["rate"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "ok_frac": res["fp64"]["ok_frac"], "evals_per_path": res["fp64"]["evals_per_path"],
+                 "paths_per_s": res["fp64"]["paths_per_s"], "kernels_ms": res["fp64"]["kernels"],
+                 "kernel_units": res["fp64"]["units"], "roofline_frac_fp64_peak": f64_frac},
+        "mixed": {"value": mixed["rate"], "ms_per_step": mixed["ms_per_step"],
+                  "ok_frac": mixed["ok_frac"], "evals_per_path": mixed["evals_per_path"],
+                  "paths_per_s": mixed["paths_per_s"], "kernels_ms": mixed["kernels"],
+                  "kernel_units": mixed["units"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(csys, z0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * hom.h - C ABI of the MI355X polyhedral-homotopy hot path (arXiv 2111.14317).
+ *
+ * The library evaluates a lifted Laurent system together with all its partial derivatives and
+ * solves the Euler and Newton directions in one consolidated solve, at many points or paths at
+ * once, on one AMD Instinct MI355X (gfx950).
+ *
+ * Notation (Sec. 2, eq. (1) and (2); Sec. 5.1):
+ *   h_k(x, t) = sum_{a in S_k} c_{k,a} x^a t^{w_k(a)},  k = 0..n-1, with x = e^z (any branch of
+ *   log) and t = e^s.  Equation k has m_k monomials; M = sum_k m_k.
+ *   A   : int8 [M][n] row-major exponent vectors, equation-major (equation 0's rows first),
+ *         |a| <= 127.
+ *   w   : double [M] liftings (non-negative; rational values allowed).
+ *   c   : complex128 [M] coefficients (interleaved re, im), passed per call.
+ *   z   : complex128 [P][n] points in log coordinates; s : double [P] (s <= 0, t = 1 <=> s = 0).
+ *
+ * Ownership and memory: every array argument of the compute calls (eval, step, track,
+ * endpoint_grad) is a caller-owned DEVICE buffer, contiguous, in the layout stated.  hom_create
+ * takes HOST arrays and copies them.  The library owns only its handle tables and workspaces.
+ *
+ * Errors: every call returns HOM_OK (0) or a negative code; hom_last_error() gives a
+ * thread-local message.  Per-point or per-path numerical outcomes go to status arrays and never
+ * fail a call.  Compute calls are asynchronous on `stream`; device faults surface at the next
+ * synchronisation.  A handle is immutable after creation, so one handle may be used from
+ * several streams at once.
+ */
+#ifndef HOM_H
+#define HOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hom_system_s *hom_system_t;
+typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
+
+/* return codes */
+#define HOM_OK 0
+#define HOM_EINVAL (-1)       /* invalid argument (null pointer, n out of range, ...) */
+#define HOM_ENOMEM (-2)       /* device allocation failed */
+#define HOM_EDEVICE (-3)      /* a HIP call failed */
+#define HOM_EUNSUPPORTED (-4) /* valid but not supported (e.g. tables too large) */
+
+/* precision of the compute calls */
+#define HOM_FP64 0  /* everything in FP64 */
+#define HOM_MIXED 1 /* FP32 exponentials, contraction and LU; FP64 exponent sums, state and
+                       decisions; FP64 endgame (see hom_track) */
+
+/* hom_eval flags */
+#define HOM_UNSCALED 1 /* multiply row k back by e^{logscale_k} (may overflow) */
+#define HOM_AFFINE 2   /* return J_x = J_z diag(e^{-z}) and H_t = e^{-s} H_s instead */
+#define HOM_EVAL_FP32 4 /* the mixed form's evaluation: FP32 exponentials and contraction
+                           (exponent sums still FP64), results widened to FP64 */
+
+/* per-path status (hom_step: OK or SINGULAR; hom_track: all) */
+#define HOM_PATH_OK 0            /* reached s = 0, endgame converged, residual <= res_tol */
+#define HOM_PATH_START 1         /* input: a fresh start point (polish at s, then track) */
+#define HOM_PATH_RUNNING 2       /* in/out: stopped at an accepted point; call again to resume */
+#define HOM_PATH_SINGULAR (-1)   /* pivot ratio below sing_ratio off the tracking phase */
+#define HOM_PATH_STEP_MIN (-2)   /* step size fell below ds_min */
+#define HOM_PATH_DIVERGED (-3)   /* |Re z_j| > div_re */
+#define HOM_PATH_NONFINITE (-4)  /* NaN or Inf off the tracking phase */
+#define HOM_PATH_POLISH_FAIL (-5) /* start point did not converge at s0 */
+#define HOM_PATH_ENDGAME_FAIL (-6) /* residual at s = 0 above res_tol */
+#define HOM_PATH_MAX_ITERS (-7)  /* iteration cap reached */
+
+/*
+ * Create a system handle (the initialisation step of Sec. 7, Alg. 1): validates the input,
+ * copies A and w to the device and builds the per-equation tables the kernels stage into LDS.
+ * n in [1, 32]; m[k] >= 1; M <= 65536.  Synchronous.  flags must be 0.
+ * Errors: HOM_EINVAL (bad argument), HOM_ENOMEM, HOM_EDEVICE, HOM_EUNSUPPORTED (tables larger
+ * than the kernels can stage).
+ */
+int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int flags,
+               hom_system_t *out);
+
+/* Release a handle (waits for the device).  NULL is accepted. */
+int hom_destroy(hom_system_t sys);
+
+/* n, M and the largest m_k of a handle (any pointer may be NULL). */
+int hom_system_info(hom_system_t sys, int *n, int64_t *M, int *m_max);
+
+/*
+ * Evaluate the extended Jacobian [J_z | H_s | H] at P points (Sec. 5.1 and 5.2; Sec. 7, Alg. 2):
+ *   G[p][k][j] = dh_k/dz_j (j < n),  G[p][k][n] = dh_k/ds,  G[p][k][n+1] = h_k,
+ * each row k multiplied by e^{-logscale[p][k]}, where logscale[p][k] is the largest
+ * <a, Re z_p> + w(a) s_p over the monomials of equation k (so no term over- or underflows).
+ * c: complex128 [M]; z: complex128 [P][n]; s: double [P]; G: complex128 [P][n][n+2];
+ * logscale: double [P][n] or NULL (zeros with HOM_UNSCALED).  flags: any of HOM_UNSCALED,
+ * HOM_AFFINE, HOM_EVAL_FP32.  P = 0 is a no-op.
+ */
+int hom_eval(hom_system_t sys, const double *c, int64_t P, const double *z, const double *s,
+             double *G, double *logscale, int flags, hom_stream_t stream);
+
+/*
+ * One evaluation plus the consolidated Euler/Newton solve at P points (Sec. 6 in its affine
+ * form; Sec. 7, Alg. 2 followed by Alg. 3): one LU with partial pivoting of J_z applied to
+ * both right-hand sides gives
+ *   dz_euler  = -J_z^{-1} H_s   (= dz/ds along the path through (z, s); Davidenko, Sec. 2.3)
+ *   dz_newton = -J_z^{-1} H     (the Newton step in z; Sec. 2.3).
+ * dz_euler, dz_newton: complex128 [P][n]; status: int32 [P] (HOM_PATH_OK, or
+ * HOM_PATH_SINGULAR when a pivot is zero or min|pivot|/max|pivot| < 1e-14).
+ * precision: HOM_FP64 or HOM_MIXED (FP32 exponentials, contraction and LU; the LU is redone in
+ * FP64 when its FP32 pivot ratio is below 1e-4).
+ */
+int hom_step(hom_system_t sys, const double *c, int64_t P, const double *z, const double *s,
+             double *dz_euler, double *dz_newton, int32_t *status, int precision,
+             hom_stream_t stream);
+
+/* Tracker constants.  The paper fixes no step control; these are this library's rules. */
+typedef struct {
+    double ds0;        /* initial step in s for fresh paths */
+    double ds_max;     /* largest step */
+    double ds_min;     /* step below which a path fails (HOM_PATH_STEP_MIN) */
+    double tol_polish; /* start point accepted when ||dz_newton||_inf <= tol_polish */
+    double tol_track;  /* corrector converged when ||dz_newton||_inf <= tol_track */
+    double tol_end;    /* endgame stops when ||dz_newton||_inf <= tol_end (1 + ||z||_inf) */
+    double res_tol;    /* endpoint OK when max_k |h_k| / sum_a |c_a x^a| <= res_tol */
+    double div_re;     /* |Re z_j| > div_re => HOM_PATH_DIVERGED */
+    double sing_ratio; /* min|pivot| / max|pivot| below this => singular */
+    int32_t max_polish; /* Newton iterations allowed at the start point */
+    int32_t max_newton; /* corrector iterations per step before the step is rejected */
+    int32_t max_end;    /* endgame Newton iterations */
+    int32_t max_steps;  /* accepted steps per call; then HOM_PATH_RUNNING */
+    int32_t max_iters;  /* eval+solve cap per path per call; then HOM_PATH_MAX_ITERS */
+    int32_t precision;  /* HOM_FP64 or HOM_MIXED */
+} hom_track_params;
+
+/* Fill `p` with this library's defaults for `precision`. */
+int hom_track_params_default(hom_track_params *p, int precision);
+
+/*
+ * Track P paths of the homotopy to t = 1 (s = 0) with the consolidated Euler/Newton step as
+ * predictor/corrector (Sec. 2.3 and Sec. 6), all paths in one persistent launch: lane groups
+ * claim paths from a device queue and refill as paths finish.
+ * z: complex128 [P][n], in: start points, out: endpoints (or the point reached).
+ * s: double [P] in/out; ds: double [P] in/out (read for RUNNING paths).
+ * status: int32 [P] in/out: HOM_PATH_START (fresh) or HOM_PATH_RUNNING (resume); other values
+ * are left untouched and the path is skipped.
+ * counters: int32 [P][4] accumulated: accepted steps, rejected steps, corrector iterations,
+ * eval+solves.  sys_idx must be NULL (single-system handle).
+ * With precision HOM_MIXED the steps run in the mixed form and every path that reaches s = 0
+ * finishes with an FP64 endgame; paths the mixed form fails are re-tracked in FP64.
+ * Resume is bitwise: calling with max_steps = k until no path is RUNNING gives the same z and
+ * s as one call (the counters then include one extra eval+solve per resume).
+ */
+int hom_track(hom_system_t sys, const double *c, int64_t P, double *z, double *s, double *ds,
+              const int32_t *sys_idx, const hom_track_params *params, int32_t *status,
+              int32_t *counters, hom_stream_t stream);
+
+/*
+ * Gradient of a real loss L(x*) on endpoints x* = e^{z_end} (t = 1) with respect to the
+ * coefficients, by the implicit function theorem (the argument behind the Davidenko equation,
+ * Sec. 2.3).  Per path: J_x^H nu = -g, computed as J_z^H nu = -conj(x*) .* g; then
+ *   grad_c[k,a] = sum_p nu_{p,k} conj(x_p*^a),
+ * summed over paths in a fixed order (bitwise reproducible).
+ * grad_x: complex128 [P][n], g = dL/dRe x + i dL/dIm x (PyTorch's convention); grad_c:
+ * complex128 [M], overwritten, same convention.  Paths whose Jacobian is singular contribute 0.
+ * precision: HOM_FP64 or HOM_MIXED (FP32 evaluation and solve).
+ */
+int hom_endpoint_grad(hom_system_t sys, const double *c, int64_t P, const double *z_end,
+                      const double *grad_x, double *grad_c, int precision, hom_stream_t stream);
+
+/*
+ * Kernel timing (tracing).  While profiling is on for the calling thread, every kernel the
+ * compute calls launch is bracketed by two hipEvents recorded on the launch stream, and the
+ * tracker kernels also count the eval+solves they perform.  hom_profile_read waits for those
+ * events and writes up to `cap` records in launch order: the kernel label as a NUL-terminated
+ * string of at most 63 characters at names[64*i], the duration in milliseconds in ms[i], and
+ * the number of eval+solves done by that launch in units[i] (-1 where not counted).  It clears
+ * the list and returns the number of records written (records beyond `cap` are dropped), or a
+ * negative error code.  At most 4096 records are kept.  Profiling allocates device memory.
+ */
+int hom_set_profiling(int on);
+int hom_profile_read(char *names, double *ms, int64_t *units, int cap);
+
+/* Message for the last error on this thread ("" if none). */
+const char *hom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOM_H */

@@ -127,7 +127,7 @@ class TrackParams:
     max_newton: int = 3
     max_end: int = 8
     max_steps: int = 100000
-    max_iters: int = 1000000
+    max_iters: int = 100000
 
     def arrays(self):
         d = np.array([self.ds0, self.ds_max, self.ds_min, self.tol_polish, self.tol_track,

@@ -1,0 +1,410 @@
+// C ABI (include/hom.h): argument validation, handles, workspaces, launches.
+#include <string.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/hom.h"
+#include "hom_internal.h"
+
+namespace hom {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+// ---- kernel timing ----
+struct ProfRec {
+  hipEvent_t a, b;
+  unsigned long long *units;  // device counter or nullptr
+  char label[64];
+};
+static thread_local bool g_prof = false;
+static thread_local std::vector<ProfRec> g_recs;
+static thread_local std::vector<hipEvent_t> g_pool;
+static thread_local hipEvent_t g_open = nullptr;
+static thread_local unsigned long long *g_open_units = nullptr;
+constexpr size_t kMaxRecs = 4096;
+
+static hipEvent_t pool_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_begin(hipStream_t stream) {
+  g_open_units = nullptr;
+  if (!g_prof || g_recs.size() >= kMaxRecs) return;
+  g_open = pool_get();
+  if (g_open) hipEventRecord(g_open, stream);
+}
+
+__global__ void k_prof_zero(unsigned long long *p) { *p = 0ull; }
+
+unsigned long long *prof_units(hipStream_t stream) {
+  if (!g_prof || !g_open) return nullptr;
+  unsigned long long *u = nullptr;
+  if (hipMalloc((void **)&u, sizeof *u) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL(k_prof_zero, dim3(1), dim3(1), 0, stream, u);
+  g_open_units = u;
+  return u;
+}
+
+void prof_end(hipStream_t stream, const char *label) {
+  if (!g_prof || !g_open) return;
+  hipEvent_t b = pool_get();
+  if (!b) return;
+  hipEventRecord(b, stream);
+  ProfRec r;
+  r.a = g_open;
+  r.b = b;
+  r.units = g_open_units;
+  g_open_units = nullptr;
+  strncpy(r.label, label, 63);
+  r.label[63] = 0;
+  g_recs.push_back(r);
+  g_open = nullptr;
+}
+
+int bucket_for(int n) {
+  for (int N : kSizes)
+    if (N >= n) return N;
+  return 0;
+}
+
+int table_ld(int N) { return ((N + 1) & 1) ? (N + 1) : (N + 2); }
+
+int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+static size_t lds_for(int N, int n, int mmax) {
+  return (size_t)mmax * n * table_ld(N) * 8 + (size_t)mmax * n * (16 + 8) + 4 * 32 + 64;
+}
+
+}  // namespace hom
+
+using namespace hom;
+
+struct hom_system_s {
+  System s;
+};
+
+#define HOM_FAIL(code, msg)   \
+  do {                        \
+    set_error(msg);           \
+    return code;              \
+  } while (0)
+
+#define HOM_HIP(call, what)                                                        \
+  do {                                                                             \
+    hipError_t _e = (call);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      set_error(std::string(what) + ": " + hipGetErrorString(_e));                 \
+      return _e == hipErrorOutOfMemory ? HOM_ENOMEM : HOM_EDEVICE;                 \
+    }                                                                              \
+  } while (0)
+
+static constexpr size_t kMaxLds = 48 * 1024;  // leaves room for per-group state
+
+extern "C" {
+
+const char *hom_last_error(void) { return g_err.c_str(); }
+
+int hom_set_profiling(int on) {
+  g_err.clear();
+  g_prof = on != 0;
+  return HOM_OK;
+}
+
+int hom_profile_read(char *names, double *ms, int64_t *units, int cap) {
+  g_err.clear();
+  if (cap < 0 || (cap > 0 && (!names || !ms || !units)))
+    HOM_FAIL(HOM_EINVAL, "hom_profile_read: bad buffers");
+  int out = 0;
+  hipError_t err = hipSuccess;
+  for (ProfRec &r : g_recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    int64_t u = -1;
+    if (r.units) {
+      unsigned long long hv = 0;
+      if (e == hipSuccess) e = hipMemcpy(&hv, r.units, sizeof hv, hipMemcpyDeviceToHost);
+      if (e != hipSuccess && err == hipSuccess) err = e;
+      u = (int64_t)hv;
+      hipFree(r.units);
+    }
+    if (out < cap) {
+      memcpy(names + 64 * out, r.label, 64);
+      ms[out] = (double)t;
+      units[out] = u;
+      ++out;
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  if (err != hipSuccess) HOM_HIP(err, "hom_profile_read");
+  return out;
+}
+
+int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int flags,
+               hom_system_t *out) {
+  g_err.clear();
+  if (!out) HOM_FAIL(HOM_EINVAL, "hom_create: out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 32) HOM_FAIL(HOM_EINVAL, "hom_create: n must be in [1, 32]");
+  if (!m || !A || !w) HOM_FAIL(HOM_EINVAL, "hom_create: m, A and w must be non-NULL");
+  if (flags != 0) HOM_FAIL(HOM_EINVAL, "hom_create: flags must be 0");
+  int64_t M = 0;
+  int mmax = 0;
+  for (int k = 0; k < n; ++k) {
+    if (m[k] < 1) HOM_FAIL(HOM_EINVAL, "hom_create: every m[k] must be >= 1");
+    M += m[k];
+    if (m[k] > mmax) mmax = m[k];
+  }
+  if (M > 65536) HOM_FAIL(HOM_EINVAL, "hom_create: M must be <= 65536");
+  for (int64_t i = 0; i < M * n; ++i)
+    if (A[i] == -128) HOM_FAIL(HOM_EINVAL, "hom_create: exponents must lie in [-127, 127]");
+  for (int64_t i = 0; i < M; ++i)
+    if (!std::isfinite(w[i]) || w[i] < 0)
+      HOM_FAIL(HOM_EINVAL, "hom_create: liftings must be finite and non-negative");
+  const int N = bucket_for(n);
+  const size_t lds = lds_for(N, n, mmax);
+  if (lds > kMaxLds)
+    HOM_FAIL(HOM_EUNSUPPORTED, "hom_create: system tables exceed the LDS budget (" +
+                                   std::to_string(lds) + " bytes)");
+  const int LD = table_ld(N);
+  std::vector<int32_t> off(n);
+  int64_t acc = 0;
+  for (int k = 0; k < n; ++k) {
+    off[k] = (int32_t)acc;
+    acc += m[k];
+  }
+  std::vector<double> T((size_t)mmax * n * LD, 0.0);
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < m[k]; ++i) {
+      double *t = &T[((size_t)i * n + k) * LD];
+      const int8_t *a = A + (size_t)(off[k] + i) * n;
+      for (int j = 0; j < n; ++j) t[j] = (double)a[j];
+      t[N] = w[off[k] + i];
+    }
+  std::vector<int32_t> A32((size_t)M * n);
+  for (size_t i = 0; i < A32.size(); ++i) A32[i] = A[i];
+
+  hom_system_s *h = new hom_system_s();
+  System &S = h->s;
+  S.n = n;
+  S.N = N;
+  S.mmax = mmax;
+  S.M = (int)M;
+  S.lds_bytes = lds;
+  auto fail = [&](hipError_t e, const char *what) {
+    set_error(std::string("hom_create: ") + what + ": " + hipGetErrorString(e));
+    hipFree(S.dT);
+    hipFree(S.dmk);
+    hipFree(S.doff);
+    hipFree(S.dA);
+    delete h;
+    return e == hipErrorOutOfMemory ? HOM_ENOMEM : HOM_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&S.device)) != hipSuccess) return fail(e, "hipGetDevice");
+  if ((e = hipMalloc(&S.dT, T.size() * 8)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMalloc(&S.dmk, n * 4)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMalloc(&S.doff, n * 4)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMalloc(&S.dA, A32.size() * 4)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMemcpy(S.dT, T.data(), T.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(S.dmk, m, n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(S.doff, off.data(), n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(S.dA, A32.data(), A32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy");
+  *out = h;
+  return HOM_OK;
+}
+
+int hom_destroy(hom_system_t h) {
+  g_err.clear();
+  if (!h) return HOM_OK;
+  hipDeviceSynchronize();
+  hipFree(h->s.dT);
+  hipFree(h->s.dmk);
+  hipFree(h->s.doff);
+  hipFree(h->s.dA);
+  delete h;
+  return HOM_OK;
+}
+
+int hom_system_info(hom_system_t h, int *n, int64_t *M, int *m_max) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_system_info: NULL handle");
+  if (n) *n = h->s.n;
+  if (M) *M = h->s.M;
+  if (m_max) *m_max = h->s.mmax;
+  return HOM_OK;
+}
+
+int hom_eval(hom_system_t h, const double *c, int64_t P, const double *z, const double *s,
+             double *G, double *logscale, int flags, hom_stream_t stream) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL handle");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_eval: P < 0");
+  if (flags & ~7) HOM_FAIL(HOM_EINVAL, "hom_eval: unknown flags");
+  if (P == 0) return HOM_OK;
+  if (!c || !z || !s || !G) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL array");
+  HOM_HIP(launch_eval(h->s, c, P, z, s, G, logscale, flags, (hipStream_t)stream), "hom_eval");
+  return HOM_OK;
+}
+
+int hom_step(hom_system_t h, const double *c, int64_t P, const double *z, const double *s,
+             double *dz_euler, double *dz_newton, int32_t *status, int precision,
+             hom_stream_t stream) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_step: NULL handle");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_step: P < 0");
+  if (precision != HOM_FP64 && precision != HOM_MIXED)
+    HOM_FAIL(HOM_EINVAL, "hom_step: precision must be HOM_FP64 or HOM_MIXED");
+  if (P == 0) return HOM_OK;
+  if (!c || !z || !s || !dz_euler || !dz_newton || !status)
+    HOM_FAIL(HOM_EINVAL, "hom_step: NULL array");
+  HOM_HIP(launch_step(h->s, c, P, z, s, dz_euler, dz_newton, status, precision,
+                      (hipStream_t)stream),
+          "hom_step");
+  return HOM_OK;
+}
+
+int hom_track_params_default(hom_track_params *p, int precision) {
+  g_err.clear();
+  if (!p) HOM_FAIL(HOM_EINVAL, "hom_track_params_default: NULL");
+  if (precision != HOM_FP64 && precision != HOM_MIXED)
+    HOM_FAIL(HOM_EINVAL, "hom_track_params_default: bad precision");
+  p->ds0 = 0.05;
+  p->ds_max = 0.5;
+  p->ds_min = 1e-10;
+  p->tol_polish = 1e-12;
+  p->tol_track = precision == HOM_MIXED ? 1e-5 : 1e-8;
+  p->tol_end = 1e-14;
+  p->res_tol = 1e-10;
+  p->div_re = 40.0;
+  p->sing_ratio = 1e-14;
+  p->max_polish = 5;
+  p->max_newton = 3;
+  p->max_end = 8;
+  p->max_steps = 100000;
+  p->max_iters = 100000;
+  p->precision = precision;
+  return HOM_OK;
+}
+
+static TrackDev to_dev(const hom_track_params *p) {
+  return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
+                  p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
+                  p->max_newton, p->max_end,    p->max_steps, p->max_iters};
+}
+
+// restore failed mixed-form paths to their start (z, s) and mark them fresh for the FP64 pass
+__global__ void k_restart_failed(int64_t P, int n, double *z, double *s, double *ds,
+                                 int32_t *status, const double *z0, const double *s0,
+                                 const double *ds0, const int32_t *st0) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int st = status[p];
+  const int was = st0[p];
+  if (st < 0 && st != HOM_PATH_MAX_ITERS && (was == HOM_PATH_START || was == HOM_PATH_RUNNING)) {
+    for (int j = 0; j < 2 * n; ++j) z[2 * p * n + j] = z0[2 * p * n + j];
+    s[p] = s0[p];
+    ds[p] = ds0[p];
+    status[p] = was;
+  }
+}
+
+int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
+              const int32_t *sys_idx, const hom_track_params *params, int32_t *status,
+              int32_t *counters, hom_stream_t stream) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_track: NULL handle");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_track: P < 0");
+  if (!params) HOM_FAIL(HOM_EINVAL, "hom_track: NULL params");
+  if (sys_idx) HOM_FAIL(HOM_EINVAL, "hom_track: sys_idx must be NULL for a single-system handle");
+  if (params->precision != HOM_FP64 && params->precision != HOM_MIXED)
+    HOM_FAIL(HOM_EINVAL, "hom_track: bad precision");
+  if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
+      params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
+      params->max_steps < 0 || params->max_iters < 1)
+    HOM_FAIL(HOM_EINVAL, "hom_track: bad params");
+  if (P == 0) return HOM_OK;
+  if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, "hom_track: NULL array");
+  hipStream_t st = (hipStream_t)stream;
+  const TrackDev pr = to_dev(params);
+  const int n = h->s.n;
+  // workspace: queue counter (+ in the mixed form, a copy of the start state)
+  size_t bytes = 256;
+  if (params->precision == HOM_MIXED) bytes += (size_t)P * (16 * n + 8 + 8 + 4) + 256;
+  char *ws = nullptr;
+  HOM_HIP(hipMallocAsync((void **)&ws, bytes, st), "hom_track: workspace");
+  unsigned long long *queue = reinterpret_cast<unsigned long long *>(ws);
+  hipError_t e = hipSuccess;
+  if (params->precision == HOM_MIXED) {
+    double *z0 = reinterpret_cast<double *>(ws + 256);
+    double *s0 = z0 + 2 * P * n;
+    double *ds0 = s0 + P;
+    int32_t *st0 = reinterpret_cast<int32_t *>(ds0 + P);
+    e = hipMemcpyAsync(z0, z, (size_t)P * 16 * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s0, s, (size_t)P * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ds0, ds, (size_t)P * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(st0, status, (size_t)P * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, true, queue, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_restart_failed, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P,
+                         n, z, s, ds, status, z0, s0, ds0, st0);
+      e = hipGetLastError();
+    }
+  }
+  // FP64 pass: the whole FP64 form, or the endgame and the fallbacks of the mixed form
+  if (e == hipSuccess) e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, false, queue, st);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  if (e != hipSuccess) HOM_HIP(e, "hom_track");
+  HOM_HIP(e2, "hom_track: free workspace");
+  return HOM_OK;
+}
+
+int hom_endpoint_grad(hom_system_t h, const double *c, int64_t P, const double *z_end,
+                      const double *grad_x, double *grad_c, int precision, hom_stream_t stream) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: NULL handle");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: P < 0");
+  if (precision != HOM_FP64 && precision != HOM_MIXED)
+    HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: bad precision");
+  if (!c || !grad_c || (P > 0 && (!z_end || !grad_x)))
+    HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: NULL array");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t elems = grad_work_elems(h->s, P);
+  double *work = nullptr;
+  HOM_HIP(hipMallocAsync((void **)&work, elems * 8, st), "hom_endpoint_grad: workspace");
+  hipError_t e = launch_grad(h->s, c, P, z_end, grad_x, grad_c, precision, work, elems, st);
+  hipError_t e2 = hipFreeAsync(work, st);
+  if (e != hipSuccess) HOM_HIP(e, "hom_endpoint_grad");
+  HOM_HIP(e2, "hom_endpoint_grad: free workspace");
+  return HOM_OK;
+}
+
+}  // extern "C"

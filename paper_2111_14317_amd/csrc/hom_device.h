@@ -1,0 +1,337 @@
+// Device building blocks of the homotopy hot path for gfx950 (wave64).
+//
+// Work mapping.  A path (or point) is owned by a group of N consecutive lanes of a wave, N = the
+// system's n rounded up to a compiled size; lane r of the group owns equation r.  A wave holds
+// G = 64 / N groups.  Lanes r >= n of a group are padding: they produce an identity row, so the
+// padded unknowns solve to zero.
+//
+//  * eval_row   (A1-A3, Sec. 5.1-5.2): lane r forms, for each monomial i of equation r, the
+//    exponent u = <a_i, z> + w_i s (a real x complex contraction over the exponent table), the
+//    row maximum M_r of Re u, the shifted term V_i = c_i exp(u - M_r), and accumulates
+//    V_i * [a_i | w_i | 1] into row r of the extended Jacobian [J_z | H_s | H].  All of this is
+//    lane-local: no cross-lane traffic during the evaluation.
+//  * lu_solve2  (A5, Sec. 6 in its affine form): LU with partial pivoting of J_z on the augmented
+//    rows, both right-hand sides (H_s, H) at once.  Rows stay in registers; the pivot search is a
+//    rotation-doubling argmax across the group and the pivot row is broadcast with ds_bpermute.
+//    Back substitution is column oriented, so every solution entry is broadcast once.
+//
+// The exponent table in LDS is laid out [i][r][LD] (monomial, equation, exponent) with the
+// lifting w in slot N and LD odd, so the n lanes of a group reading monomial i of their own
+// equations hit distinct LDS banks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hom {
+
+constexpr double kInv2Pi = 0.159154943091895335768883763372514362;  // 1 / (2 pi)
+constexpr double kLog2e = 1.44269504088896340735992468100189214;
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// a - l * b
+template <typename T>
+__device__ __forceinline__ Cx<T> cfnms(Cx<T> a, Cx<T> l, Cx<T> b) {
+  Cx<T> r;
+  r.x = fma(-l.x, b.x, fma(l.y, b.y, a.x));
+  r.y = fma(-l.x, b.y, fma(-l.y, b.x, a.y));
+  return r;
+}
+
+// 1/x: hardware reciprocal estimate refined by Newton steps (two in FP64: ~1 ulp), instead of the
+// IEEE division sequence.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float fast_rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+template <typename T>
+__device__ __forceinline__ Cx<T> shfl_cx(Cx<T> v, int src) {
+  return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
+
+// Stride of one (monomial, equation) record in the exponent table: N exponents, the lifting, and
+// one pad slot when needed to make the stride odd (conflict-free LDS reads across a group).
+template <int N>
+struct TableLD {
+  static constexpr int value = ((N + 1) & 1) ? (N + 1) : (N + 2);
+};
+
+template <int N>
+struct Geo {
+  static constexpr int G = 64 / N;  // groups per wave
+  int lane, g, r, base;
+  bool valid;  // lane belongs to a full group
+  __device__ __forceinline__ Geo() {
+    lane = threadIdx.x & 63;
+    g = lane / N;
+    r = lane - g * N;
+    base = g * N;
+    valid = g < G;
+  }
+};
+
+// Group-wide argmax of (mag, idx) with ties to the lowest idx, by rotation doubling: after the
+// step with offset o every lane holds the best of the window [r, r + 2o) (mod N).  Max is
+// idempotent, so windows wrapping onto themselves are harmless.  Every lane of the wave must
+// execute this (the shuffles read other lanes).
+template <int N, typename T>
+__device__ __forceinline__ void group_argmax(T &mag, int &idx, int r, int base) {
+#pragma unroll
+  for (int off = 1; off < N; off <<= 1) {
+    int t = r + off;
+    t = t >= N ? t - N : t;
+    const int src = base + t;
+    const T om = __shfl(mag, src, 64);
+    const int oi = __shfl(idx, src, 64);
+    const bool take = (om > mag) || (om == mag && oi < idx);
+    mag = take ? om : mag;
+    idx = take ? oi : idx;
+  }
+}
+
+// Maximum over the group (every lane ends with it); NaN propagates.
+template <int N, typename T>
+__device__ __forceinline__ T group_max(T v, int r, int base) {
+#pragma unroll
+  for (int off = 1; off < N; off <<= 1) {
+    int t = r + off;
+    t = t >= N ? t - N : t;
+    const T o = __shfl(v, base + t, 64);
+    v = (o > v || o != o) ? o : v;  // propagates NaN
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// tables staged in LDS
+// ------------------------------------------------------------------------------------------
+struct SysDev {
+  int n;              // true number of equations / unknowns
+  int mmax;           // largest m_k
+  int M;              // total monomials
+  const double *T;    // [mmax][n][LD] exponents (as doubles, zero padded to N) + lifting
+  const int32_t *mk;  // [n]
+  const int32_t *off; // [n] offset of equation k in the equation-major arrays
+};
+
+// LDS image of a system: exponent table, coefficients in table order, |c|, m_k.
+template <int N>
+struct SysLds {
+  const double *T;
+  const Cx<double> *C;
+  const double *Cabs;
+  const int32_t *mk;
+  int n, mmax;
+};
+
+template <int N>
+__host__ __device__ constexpr size_t lds_table_bytes(int n, int mmax) {
+  return (size_t)mmax * n * TableLD<N>::value * 8 + (size_t)mmax * n * (16 + 8) + 4 * 32 + 64;
+}
+
+// Cooperative copy of the tables into LDS (whole block).  c: complex128 [M] equation-major.
+template <int N>
+__device__ SysLds<N> stage_tables(char *smem, const SysDev &sd, const double *__restrict__ c) {
+  constexpr int LD = TableLD<N>::value;
+  const int n = sd.n, mmax = sd.mmax;
+  double *sT = reinterpret_cast<double *>(smem);
+  const int nT = mmax * n * LD;
+  Cx<double> *sC = reinterpret_cast<Cx<double> *>(sT + nT);
+  double *sA = reinterpret_cast<double *>(sC + mmax * n);
+  int32_t *sM = reinterpret_cast<int32_t *>(sA + mmax * n);
+  for (int idx = threadIdx.x; idx < nT; idx += blockDim.x) sT[idx] = sd.T[idx];
+  for (int idx = threadIdx.x; idx < mmax * n; idx += blockDim.x) {
+    const int i = idx / n, r = idx - (idx / n) * n;
+    Cx<double> v = {0.0, 0.0};
+    if (i < sd.mk[r]) {
+      const int q = sd.off[r] + i;
+      v.x = c[2 * q];
+      v.y = c[2 * q + 1];
+    }
+    sC[idx] = v;
+    sA[idx] = sqrt(v.x * v.x + v.y * v.y);
+  }
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) sM[idx] = sd.mk[idx];
+  __syncthreads();
+  return SysLds<N>{sT, sC, sA, sM, n, mmax};
+}
+
+// ------------------------------------------------------------------------------------------
+// A1-A3: one row of [J_z | H_s | H] at (z, s), scaled by e^{-M_r}
+// ------------------------------------------------------------------------------------------
+// row[j], j < N: dh_r/dz_j;  row[N]: dh_r/ds;  row[N+1]: h_r.  logM = M_r; absum = sum |V_i|.
+// T is the precision of the exponentials and of the contraction (double, or float for the
+// mixed form).  The exponent sums u are always formed in FP64.
+template <int N, typename T>
+__device__ __forceinline__ void eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
+                                         const double (&zi)[N], double s, Cx<T> (&row)[N + 2],
+                                         double &logM, T &absum) {
+  constexpr int LD = TableLD<N>::value;
+#pragma unroll
+  for (int j = 0; j < N + 2; ++j) row[j] = {T(0), T(0)};
+  absum = T(0);
+  logM = 0.0;
+  if (r >= S.n) {  // padding lane: identity row for unknown r
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j == r) row[j].x = T(1);
+    absum = T(1);
+    return;
+  }
+  const int n = S.n, mr = S.mk[r];
+  // pass 1: row maximum of Re u
+  double M = -INFINITY;
+#pragma unroll 1
+  for (int i = 0; i < mr; ++i) {
+    const double *t = S.T + (i * n + r) * LD;
+    double e = t[N] * s;
+#pragma unroll
+    for (int j = 0; j < N; ++j) e = fma(t[j], zr[j], e);
+    M = fmax(M, e);
+  }
+  logM = M;
+  // pass 2: shifted exponentials and the contraction with [a | w | 1]
+#pragma unroll 1
+  for (int i = 0; i < mr; ++i) {
+    const double *t = S.T + (i * n + r) * LD;
+    double re = t[N] * s, im = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      re = fma(t[j], zr[j], re);
+      im = fma(t[j], zi[j], im);
+    }
+    double turns = im * kInv2Pi;
+    turns -= rint(turns);  // phase in turns, [-1/2, 1/2]
+    const Cx<double> cc = S.C[i * n + r];
+    Cx<T> v;
+    T mag;
+    if constexpr (sizeof(T) == 8) {
+      mag = exp(re - M);
+      double sn, cs;
+      sincospi(2.0 * turns, &sn, &cs);
+      v.x = mag * (cc.x * cs - cc.y * sn);
+      v.y = mag * (cc.x * sn + cc.y * cs);
+      absum += mag * S.Cabs[i * n + r];
+    } else {
+      mag = __builtin_amdgcn_exp2f((float)((re - M) * kLog2e));
+      const float tf = (float)turns;
+      const float sn = __builtin_amdgcn_sinf(tf), cs = __builtin_amdgcn_cosf(tf);
+      const float cx = (float)cc.x, cy = (float)cc.y;
+      v.x = mag * (cx * cs - cy * sn);
+      v.y = mag * (cx * sn + cy * cs);
+      absum += mag * (float)S.Cabs[i * n + r];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const T a = (T)t[j];
+      row[j].x = fma(a, v.x, row[j].x);
+      row[j].y = fma(a, v.y, row[j].y);
+    }
+    const T wv = (T)t[N];
+    row[N].x = fma(wv, v.x, row[N].x);
+    row[N].y = fma(wv, v.y, row[N].y);
+    row[N + 1].x += v.x;
+    row[N + 1].y += v.y;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// A5: LU with partial pivoting across the group, two right-hand sides
+// ------------------------------------------------------------------------------------------
+// On return myE / myN hold entry r of dE = -J^{-1} H_s and dN = -J^{-1} H, nrmE / nrmN the
+// max-modulus norms of dE and dN over the true unknowns (identical in every lane; NaN
+// propagates), ratio = min|pivot| / max|pivot| over the true columns.  Returns true when a
+// pivot is zero or not finite.  Every lane of the wave must call this (it shuffles).
+template <int N, typename T>
+__device__ __forceinline__ bool lu_solve2(Cx<T> (&row)[N + 2], int r, int base, int n, Cx<T> &myE,
+                                          Cx<T> &myN, double &nrmE, double &nrmN, T &ratio) {
+  bool used = false;
+  int my_order = N;
+  Cx<T> inv_mine = {T(0), T(0)};
+  int pl[N];
+  T pmin2 = T(INFINITY), pmax2 = T(0);
+  bool sing = false;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T mag = used ? T(-1) : (row[j].x * row[j].x + row[j].y * row[j].y);
+    int idx = r;
+    group_argmax<N, T>(mag, idx, r, base);
+    pl[j] = idx;
+    const int src = base + idx;
+    const Cx<T> pv = shfl_cx(row[j], src);
+    sing |= !(mag > T(0) && mag < T(INFINITY));
+    if (j < n) {
+      pmin2 = fmin(pmin2, mag);
+      pmax2 = fmax(pmax2, mag);
+    }
+    const T id = fast_rcp(mag);
+    const Cx<T> inv = {pv.x * id, -pv.y * id};
+    const bool me = (r == idx);
+    Cx<T> l = {T(0), T(0)};
+    if (!used && !me) l = cmul(row[j], inv);
+    if (me) {
+      used = true;
+      my_order = j;
+      inv_mine = inv;
+    }
+#pragma unroll
+    for (int col = j + 1; col < N + 2; ++col) {
+      const Cx<T> pc = shfl_cx(row[col], src);
+      row[col] = cfnms(row[col], l, pc);
+    }
+  }
+  double nE = 0.0, nN = 0.0;
+  myE = {T(0), T(0)};
+  myN = {T(0), T(0)};
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    const int src = base + pl[j];
+    const Cx<T> e = cmul(row[N], inv_mine), q = cmul(row[N + 1], inv_mine);
+    const Cx<T> xe = shfl_cx(e, src), xq = shfl_cx(q, src);
+    if (my_order < j) {
+      row[N] = cfnms(row[N], row[j], xe);
+      row[N + 1] = cfnms(row[N + 1], row[j], xq);
+    }
+    if (j < n) {  // squared moduli; one square root at the end (sqrt is monotone)
+      const double ae = (double)xe.x * xe.x + (double)xe.y * xe.y;
+      const double aq = (double)xq.x * xq.x + (double)xq.y * xq.y;
+      nE = (ae > nE || ae != ae) ? ae : nE;
+      nN = (aq > nN || aq != aq) ? aq : nN;
+    }
+    if (r == j) {
+      myE = {-xe.x, -xe.y};
+      myN = {-xq.x, -xq.y};
+    }
+  }
+  nrmE = sqrt(nE);
+  nrmN = sqrt(nN);
+  ratio = sqrt(pmin2 / pmax2);
+  return sing;
+}
+
+// Value of a replicated register array at a runtime index (select chain, no scratch).
+template <int N>
+__device__ __forceinline__ double pick(const double (&a)[N], int r) {
+  double v = a[0];
+#pragma unroll
+  for (int j = 1; j < N; ++j) v = (j == r) ? a[j] : v;
+  return v;
+}
+
+}  // namespace hom

@@ -1,0 +1,225 @@
+// Batched evaluation (A1-A4) and evaluation + consolidated Euler/Newton solve (A1-A5).
+//
+// hom_eval : G = [J_z | H_s | H] per point, rows scaled by e^{-M_k} (Sec. 5.1-5.2; Alg. 2).
+// hom_step : the same evaluation kept in registers, then one LU with partial pivoting of J_z
+//            applied to both right-hand sides (Sec. 6 in its affine form; Alg. 3).
+// One group of N lanes per point, grid-stride over points; tables staged once per block.
+#include <stdio.h>
+
+#include "hom_internal.h"
+
+namespace hom {
+
+constexpr int kBlock = 256;
+
+template <int N>
+__device__ __forceinline__ void load_point(const double *__restrict__ z, int64_t p, int n,
+                                           double (&zr)[N], double (&zi)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (j < n) {
+      zr[j] = z[2 * (p * n + j)];
+      zi[j] = z[2 * (p * n + j) + 1];
+    } else {
+      zr[j] = 0.0;
+      zi[j] = 0.0;
+    }
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kBlock) k_eval(SysDev sd, const double *__restrict__ c,
+                                                 int64_t P, const double *__restrict__ z,
+                                                 const double *__restrict__ s,
+                                                 double *__restrict__ G,
+                                                 double *__restrict__ logscale, int flags) {
+  extern __shared__ __align__(16) char smem[];
+  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const Geo<N> geo;
+  if (!geo.valid) return;
+  const int n = sd.n, r = geo.r;
+  const int64_t gpb = (kBlock / 64) * Geo<N>::G;
+  const int64_t stride = (int64_t)gridDim.x * gpb;
+  for (int64_t p = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g; p < P;
+       p += stride) {
+    double zr[N], zi[N];
+    load_point<N>(z, p, n, zr, zi);
+    const double sp = s[p];
+    Cx<T> row[N + 2];
+    double M;
+    T absum;
+    eval_row<N, T>(S, r, zr, zi, sp, row, M, absum);
+    if (r >= n) continue;
+    const double scale = (flags & 1) ? exp(M) : 1.0;  // HOM_UNSCALED
+    double *Gr = G + 2 * ((p * n + r) * (n + 2));
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if (j < n) {
+        Cx<double> v = {(double)row[j].x * scale, (double)row[j].y * scale};
+        Gr[2 * j] = v.x;
+        Gr[2 * j + 1] = v.y;
+      }
+    }
+    if (flags & 2) {  // HOM_AFFINE: J_x = J_z diag(e^{-z}), in a loop of its own
+      for (int j = 0; j < n; ++j) {
+        double zre = z[2 * (p * n + j)], zim = z[2 * (p * n + j) + 1];
+        double sn, cs;
+        sincos(-zim, &sn, &cs);
+        const double mag = exp(-zre);
+        const Cx<double> v = cmul(Cx<double>{Gr[2 * j], Gr[2 * j + 1]}, Cx<double>{mag * cs, mag * sn});
+        Gr[2 * j] = v.x;
+        Gr[2 * j + 1] = v.y;
+      }
+    }
+    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // H_t = e^{-s} H_s
+    Gr[2 * n] = (double)row[N].x * fs;
+    Gr[2 * n + 1] = (double)row[N].y * fs;
+    Gr[2 * n + 2] = (double)row[N + 1].x * scale;
+    Gr[2 * n + 3] = (double)row[N + 1].y * scale;
+    if (logscale) logscale[p * n + r] = (flags & 1) ? 0.0 : M;
+  }
+}
+
+// Evaluation + consolidated solve.  The loop over points is wave-uniform (the LU shuffles);
+// groups past the end compute on a dummy point and store nothing.
+template <int N, bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__restrict__ c,
+                                                 int64_t P, const double *__restrict__ z,
+                                                 const double *__restrict__ s,
+                                                 double *__restrict__ dE,
+                                                 double *__restrict__ dN,
+                                                 int32_t *__restrict__ status) {
+  extern __shared__ __align__(16) char smem[];
+  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const Geo<N> geo;
+  const int n = sd.n, r = geo.r;
+  const int64_t gpb = (kBlock / 64) * Geo<N>::G;
+  const int64_t stride = (int64_t)gridDim.x * gpb;
+  const int64_t p0 = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g;
+  for (int64_t it = 0;; ++it) {
+    const int64_t p = p0 + it * stride;
+    const bool act = geo.valid && p < P;
+    if (!__any(act)) break;
+    double zr[N], zi[N];
+    load_point<N>(z, act ? p : 0, act ? n : 0, zr, zi);
+    const double sp = act ? s[p] : 0.0;
+    double M, nE, nN;
+    Cx<double> e, q;
+    bool sing;
+    double ratio;
+    if constexpr (MIXED) {
+      Cx<float> row[N + 2], ef, qf;
+      float absum, rf;
+      eval_row<N, float>(S, r, zr, zi, sp, row, M, absum);
+      sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
+      e = {ef.x, ef.y};
+      q = {qf.x, qf.y};
+      ratio = rf;
+      // near-singular in FP32: redo this point's evaluation and LU in FP64
+      const bool redo = act && (sing || !(rf >= 1e-4f));
+      if (__any(redo)) {
+        Cx<double> rowd[N + 2], ed, qd;
+        double ad, rd, nEd, nNd;
+        eval_row<N, double>(S, r, zr, zi, sp, rowd, M, ad);
+        const bool sd2 = lu_solve2<N, double>(rowd, r, geo.base, n, ed, qd, nEd, nNd, rd);
+        if (redo) {
+          e = ed;
+          q = qd;
+          sing = sd2;
+          ratio = rd;
+        }
+      }
+    } else {
+      Cx<double> row[N + 2];
+      double absum;
+      eval_row<N, double>(S, r, zr, zi, sp, row, M, absum);
+      sing = lu_solve2<N, double>(row, r, geo.base, n, e, q, nE, nN, ratio);
+    }
+    if (act) {
+      if (r < n) {
+        dE[2 * (p * n + r)] = e.x;
+        dE[2 * (p * n + r) + 1] = e.y;
+        dN[2 * (p * n + r)] = q.x;
+        dN[2 * (p * n + r) + 1] = q.y;
+      }
+      if (r == 0) status[p] = (sing || !(ratio >= 1e-14)) ? -1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static int grid_for(int64_t P, int groups_per_block) {
+  const int64_t need = (P + groups_per_block - 1) / groups_per_block;
+  const int64_t cap = (int64_t)num_cus() * 8;
+  return (int)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+#define HOM_SWITCH(N, CALL)            \
+  switch (N) {                         \
+    case 2: { constexpr int NN = 2; CALL; } \
+    case 3: { constexpr int NN = 3; CALL; } \
+    case 4: { constexpr int NN = 4; CALL; } \
+    case 5: { constexpr int NN = 5; CALL; } \
+    case 6: { constexpr int NN = 6; CALL; } \
+    case 7: { constexpr int NN = 7; CALL; } \
+    case 8: { constexpr int NN = 8; CALL; } \
+    case 10: { constexpr int NN = 10; CALL; } \
+    case 12: { constexpr int NN = 12; CALL; } \
+    case 16: { constexpr int NN = 16; CALL; } \
+    case 20: { constexpr int NN = 20; CALL; } \
+    case 24: { constexpr int NN = 24; CALL; } \
+    case 32: { constexpr int NN = 32; CALL; } \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <int N>
+static hipError_t eval_n(const System &S, const double *c, int64_t P, const double *z,
+                         const double *s, double *G, double *logscale, int flags,
+                         hipStream_t stream) {
+  const int gpb = (kBlock / 64) * Geo<N>::G;
+  char label[64];
+  snprintf(label, sizeof label, "k_eval<%d,%s>", N, (flags & 4) ? "fp32" : "fp64");
+  prof_begin(stream);
+  if (flags & 4)
+    hipLaunchKernelGGL((k_eval<N, float>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
+                       stream, S.dev(), c, P, z, s, G, logscale, flags);
+  else
+    hipLaunchKernelGGL((k_eval<N, double>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
+                       stream, S.dev(), c, P, z, s, G, logscale, flags);
+  prof_end(stream, label);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t step_n(const System &S, const double *c, int64_t P, const double *z,
+                         const double *s, double *dE, double *dN, int32_t *status,
+                         int precision, hipStream_t stream) {
+  const int gpb = (kBlock / 64) * Geo<N>::G;
+  char label[64];
+  snprintf(label, sizeof label, "k_step<%d,%s>", N, precision == 1 ? "mixed" : "fp64");
+  prof_begin(stream);
+  if (precision == 1)
+    hipLaunchKernelGGL((k_step<N, true>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
+                       stream, S.dev(), c, P, z, s, dE, dN, status);
+  else
+    hipLaunchKernelGGL((k_step<N, false>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
+                       stream, S.dev(), c, P, z, s, dE, dN, status);
+  prof_end(stream, label);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const System &S, const double *c, int64_t P, const double *z,
+                       const double *s, double *G, double *logscale, int flags,
+                       hipStream_t stream) {
+  HOM_SWITCH(S.N, return eval_n<NN>(S, c, P, z, s, G, logscale, flags, stream))
+}
+
+hipError_t launch_step(const System &S, const double *c, int64_t P, const double *z,
+                       const double *s, double *dE, double *dN, int32_t *status, int precision,
+                       hipStream_t stream) {
+  HOM_SWITCH(S.N, return step_n<NN>(S, c, P, z, s, dE, dN, status, precision, stream))
+}
+
+}  // namespace hom

@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports every symbol include/hom.h declares; argument
+validation answers without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hom.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hom_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    import paper_2111_14317_amd as hom
+    names = _declared()
+    assert set(names) == set(hom.EXPORTED), names
+    lib = ctypes.CDLL(hom.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    import paper_2111_14317_amd as hom
+    lib = hom.lib
+    out = ctypes.c_void_p()
+    m = np.array([2, 2], np.int32)
+    A = np.zeros((4, 2), np.int8)
+    w = np.zeros(4)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.hom_create(0, P(m), P(A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert lib.hom_create(33, P(m), P(A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert b"n must be" in lib.hom_last_error()
+    bad_m = np.array([2, 0], np.int32)
+    assert lib.hom_create(2, P(bad_m), P(A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    bad_w = np.array([0.0, -1.0, 0.0, 0.0])
+    assert lib.hom_create(2, P(m), P(A), P(bad_w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    bad_A = A.copy(); bad_A[0, 0] = -128
+    assert lib.hom_create(2, P(m), P(bad_A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert lib.hom_create(2, P(m), P(A), P(w), 1, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert lib.hom_create(2, None, P(A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert lib.hom_eval(None, None, 0, None, None, None, None, 0, None) == hom.HOM_EINVAL
+    assert lib.hom_step(None, None, 0, None, None, None, None, None, 0, None) == hom.HOM_EINVAL
+    assert lib.hom_destroy(None) == hom.HOM_OK
+    p = hom.TrackParams()
+    assert lib.hom_track_params_default(ctypes.byref(p), 7) == hom.HOM_EINVAL
+    assert lib.hom_track_params_default(ctypes.byref(p), hom.MIXED) == hom.HOM_OK
+    assert p.tol_track == 1e-5 and p.res_tol == 1e-10
+
+
+def test_default_params_match_oracle_defaults():
+    """Both sides run the same tracker rules with the same constants."""
+    import oracle
+    import paper_2111_14317_amd as hom
+    p = hom.default_params(hom.FP64)
+    o = oracle.TrackParams()
+    for f in ("ds0", "ds_max", "ds_min", "tol_polish", "tol_track", "tol_end", "res_tol", "div_re",
+              "sing_ratio", "max_polish", "max_newton", "max_end", "max_steps", "max_iters"):
+        assert getattr(p, f) == getattr(o, f), f

@@ -1,0 +1,181 @@
+"""GPU parity of hom_eval and hom_step against the oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import cond_inf, eval_err, eval_err_fp32, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hom():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2111_14317_amd as hom
+    return hom
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _uneven_system(seed=3, n=5):
+    rng = np.random.default_rng(seed)
+    m = rng.integers(2, 9, size=n)
+    return W.random_system(n, m, W._uniform_exps(-3, 3), "unit", 40, rng, rng, rng), rng
+
+
+CASES = [("c1", 4096), ("c2", 8191), ("c5", 3001)]
+
+
+@pytest.mark.parametrize("cfg,P", CASES)
+def test_eval_fp64(hom, cfg, P):
+    say(f"[eval fp64] {cfg} P={P}")
+    sys, z, s = W.config_system(cfg, P=P)
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s)
+    Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+    err = eval_err(_np(G), _np(L), Go, Lo, den)
+    say(f"  max scaled err {err.max():.3e}")
+    assert err.max() <= 1e-12
+    np.testing.assert_allclose(_np(L), Lo, rtol=0, atol=1e-12 * (1 + np.abs(Lo).max()))
+
+
+@pytest.mark.parametrize("cfg,P", CASES)
+def test_eval_fp32_form(hom, cfg, P):
+    """The mixed form's evaluation: relative (componentwise scaled) error <= 1e-5."""
+    say(f"[eval fp32] {cfg} P={P}")
+    sys, z, s = W.config_system(cfg, P=P)
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s, flags=hom.EVAL_FP32)
+    Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+    err = eval_err_fp32(_np(G), _np(L), Go, Lo, den)
+    say(f"  max scaled err {err.max():.3e}  median {np.median(err):.3e}")
+    assert err.max() <= 1e-5
+
+
+def test_eval_flags(hom):
+    say("[eval flags] c1 unscaled/affine")
+    sys, z, s = W.config_system("c1", P=513)
+    h = hom.System.from_workload(sys)
+    Gu, Lu = hom.eval(h, sys.c, z, s, flags=hom.UNSCALED)
+    Go, _ = oracle.eval(sys, sys.c, z, s, scaled=False)
+    assert np.all(_np(Lu) == 0)
+    np.testing.assert_allclose(_np(Gu), Go, rtol=1e-12, atol=1e-300)
+    Ga, _ = hom.eval(h, sys.c, z, s, flags=hom.UNSCALED | hom.AFFINE)
+    Ga = _np(Ga)
+    n = sys.n
+    np.testing.assert_allclose(Ga[:, :, :n], Go[:, :, :n] * np.exp(-z)[:, None, :], rtol=1e-12)
+    np.testing.assert_allclose(Ga[:, :, n], Go[:, :, n] * np.exp(-s)[:, None], rtol=1e-12)
+
+
+def test_eval_edge_cases(hom):
+    say("[eval edge] uneven m_k, n=1, n=9 padding, P=1, underflow")
+    sys, rng = _uneven_system()
+    z, s = W.random_points(sys.n, 777, rng)
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s)
+    Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+    assert eval_err(_np(G), _np(L), Go, Lo, den).max() <= 1e-12
+    for n, m in ((1, 3), (9, 5), (11, 4)):
+        sys = W.random_system(n, m, W._uniform_exps(-2, 2), "unit", 30, rng, rng, rng)
+        z, s = W.random_points(n, 1 if n == 1 else 97, rng)
+        h = hom.System.from_workload(sys)
+        G, L = hom.eval(h, sys.c, z, s)
+        Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+        assert eval_err(_np(G), _np(L), Go, Lo, den).max() <= 1e-12, n
+    # t^w far below the FP64 range
+    sys = W.random_system(4, 6, W._uniform_exps(-2, 2), "unit", 255, rng, rng, rng)
+    sys = sys.with_lifting(sys.w + 250.0)
+    z, s = W.random_points(4, 64, rng)
+    s[:] = -8.0
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s)
+    Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+    assert np.isfinite(_np(G)).all()
+    assert eval_err(_np(G), _np(L), Go, Lo, den).max() <= 1e-12
+    # P = 0 is a no-op
+    G0, L0 = hom.eval(h, sys.c, z[:0], s[:0])
+    assert G0.shape[0] == 0
+
+
+def test_eval_full_size_sampled(hom):
+    """The full 65536-point n=10 workload; a seeded sample of 2048 points against the oracle."""
+    say("[eval full] c2 P=65536 sampled")
+    sys, z, s = W.config_system("c2")
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s)
+    idx = np.random.default_rng(0).choice(len(s), 2048, replace=False)
+    Go, Lo, den = oracle.eval(sys, sys.c, z[idx], s[idx], with_den=True)
+    assert eval_err(_np(G)[idx], _np(L)[idx], Go, Lo, den).max() <= 1e-12
+
+
+def _dir_err(a, b):
+    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-300)
+
+
+@pytest.mark.parametrize("cfg,P", CASES)
+def test_step_fp64(hom, cfg, P):
+    say(f"[step fp64] {cfg} P={P}")
+    sys, z, s = W.config_system(cfg, P=P)
+    h = hom.System.from_workload(sys)
+    dE, dN, st = hom.step(h, sys.c, z, s)
+    oE, oN, ost, ratio = oracle.step(sys, sys.c, z, s)
+    kappa = cond_inf(sys, sys.c, z, s)
+    ok = (kappa <= 1e3) & (ost == 0)
+    eE, eN = _dir_err(_np(dE), oE), _dir_err(_np(dN), oN)
+    say(f"  kappa<=1e3: {ok.sum()}/{P}  max err E {eE[ok].max():.3e} N {eN[ok].max():.3e}")
+    assert eE[ok].max() <= 1e-12 and eN[ok].max() <= 1e-12
+    # everywhere else: within the condition number
+    fin = ost == 0
+    tol = np.maximum(1e-12, 1e-15 * kappa)
+    assert (eE[fin] <= tol[fin] * 100).mean() > 0.999
+    assert np.array_equal(_np(st) == 0, (ost == 0) & (ratio >= 1e-14))
+
+
+@pytest.mark.parametrize("cfg,P", CASES)
+def test_step_mixed(hom, cfg, P):
+    say(f"[step mixed] {cfg} P={P}")
+    sys, z, s = W.config_system(cfg, P=P)
+    h = hom.System.from_workload(sys)
+    dE, dN, st = hom.step(h, sys.c, z, s, precision=hom.MIXED)
+    oE, oN, ost, _ = oracle.step(sys, sys.c, z, s)
+    kappa = cond_inf(sys, sys.c, z, s)
+    ok = (kappa <= 100) & (ost == 0)
+    eE, eN = _dir_err(_np(dE), oE), _dir_err(_np(dN), oN)
+    say(f"  kappa<=100: {ok.sum()}/{P}  max err E {eE[ok].max():.3e} N {eN[ok].max():.3e}")
+    assert eE[ok].max() <= 1e-5 and eN[ok].max() <= 1e-5
+
+
+def test_step_full_size_sampled(hom):
+    say("[step full] c2 P=65536 sampled, fp64 and mixed")
+    sys, z, s = W.config_system("c2")
+    h = hom.System.from_workload(sys)
+    idx = np.random.default_rng(1).choice(len(s), 2048, replace=False)
+    oE, oN, ost, _ = oracle.step(sys, sys.c, z[idx], s[idx])
+    kappa = cond_inf(sys, sys.c, z[idx], s[idx])
+    for prec, tol, kmax in ((hom.FP64, 1e-12, 1e3), (hom.MIXED, 1e-5, 1e2)):
+        dE, dN, st = hom.step(h, sys.c, z, s, precision=prec)
+        ok = (kappa <= kmax) & (ost == 0)
+        assert _dir_err(_np(dE)[idx], oE)[ok].max() <= tol
+        assert _dir_err(_np(dN)[idx], oN)[ok].max() <= tol
+
+
+def test_step_singular_and_nan(hom):
+    say("[step edge] singular system, NaN point")
+    rng = np.random.default_rng(2)
+    sys = W.random_system(3, 4, W._uniform_exps(-2, 2), "unit", 5, rng, rng, rng)
+    A, c, w = sys.A.copy(), sys.c.copy(), sys.w.copy()
+    A[4:8], c[4:8], w[4:8] = A[0:4], 2.0 * c[0:4], w[0:4]
+    bad = W.System(3, sys.m, A, w, c)
+    z, s = W.random_points(3, 40, rng)
+    h = hom.System.from_workload(bad)
+    for prec in (hom.FP64, hom.MIXED):
+        _, _, st = hom.step(h, bad.c, z, s, precision=prec)
+        assert (_np(st) == -1).all()
+    h = hom.System.from_workload(sys)
+    z[3, 1] = np.nan
+    _, _, st = hom.step(h, sys.c, z, s)
+    assert _np(st)[3] == -1 and (np.delete(_np(st), 3) == 0).all()

@@ -1,0 +1,142 @@
+"""GPU parity of hom_track against the oracle's tracker (same rules, same constants)."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import workloads as W
+from gpu_util import mod2pi_dist, say, torch_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hom():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2111_14317_amd as hom
+    return hom
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _key(z, digits=6):
+    return {tuple(v) for v in np.round(np.c_[z.real, np.mod(z.imag + 1e-7, 2 * np.pi)] * 10 ** digits)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c1_all_mixed_volume_paths(hom, prec):
+    """Every mixed-volume path of the tiny system, one handle per mixed cell: endpoints match
+    the oracle's, are distinct, and are roots (residual <= 1e-10)."""
+    say(f"[track c1 all cells] {prec}")
+    base, cells = W.c1_cells()
+    precision = hom.FP64 if prec == "fp64" else hom.MIXED
+    gpu_end, ora_end = [], []
+    for csys, info, z0 in cells:
+        h = hom.System.from_workload(csys)
+        st = hom.track(h, csys.c, z0, -32.0, hom.default_params(precision))
+        assert (_np(st.status) == 0).all(), _np(st.status)
+        gpu_end.append(_np(st.z))
+        ze, _, _, ost, _ = oracle.track(csys, csys.c, z0, -32.0)
+        ora_end.append(ze)
+    g, o = np.concatenate(gpu_end), np.concatenate(ora_end)
+    assert mod2pi_dist(g, o).max() <= 1e-12
+    assert len(_key(g)) == pins.mixed_volume(base) == len(g)
+    assert oracle.residual(base, base.c, g).max() <= 1e-10
+
+
+def test_fp64_matches_oracle_per_path(hom):
+    """n=8 planted-cell paths: same status and same endpoint per path; counters close."""
+    say("[track c5 fp64 per-path] P=512")
+    csys, cell, z0 = W.planted_config("c5", P=512)
+    p = oracle.TrackParams()
+    h = hom.System.from_workload(csys)
+    st = hom.track(h, csys.c, z0, -32.0, torch_params(hom, p, hom.FP64))
+    ze, se, _, ost, ocnt = oracle.track(csys, csys.c, z0, -32.0, p)
+    gst = _np(st.status)
+    both = (gst == 0) & (ost == 0)
+    say(f"  ok gpu {np.mean(gst == 0):.4f} oracle {np.mean(ost == 0):.4f}")
+    assert both.mean() >= 0.99
+    d = mod2pi_dist(_np(st.z)[both], ze[both])
+    assert np.quantile(d, 0.99) <= 1e-12
+    gc = _np(st.counters)
+    assert abs(gc[:, 3].mean() / ocnt[:, 3].mean() - 1) < 0.02
+    assert oracle.residual(csys, csys.c, _np(st.z)[gst == 0]).max() <= 1e-10
+
+
+def test_mixed_matches_fp64_endpoints(hom):
+    say("[track c5 mixed] P=512")
+    csys, cell, z0 = W.planted_config("c5", P=512)
+    h = hom.System.from_workload(csys)
+    a = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64))
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
+    sa, sb = _np(a.status), _np(b.status)
+    assert (sb == 0).mean() >= 0.99
+    both = (sa == 0) & (sb == 0)
+    d = mod2pi_dist(_np(a.z)[both], _np(b.z)[both])
+    assert np.quantile(d, 0.99) <= 1e-10
+    assert oracle.residual(csys, csys.c, _np(b.z)[sb == 0]).max() <= 1e-10
+
+
+def test_c2_subset_distinct_roots(hom):
+    """n=10: 4096 planted-cell paths in both forms; >= 99.9% OK, distinct endpoints, residuals."""
+    say("[track c2 subset] P=4096")
+    csys, cell, z0 = W.planted_config("c2", P=4096)
+    h = hom.System.from_workload(csys)
+    for prec in (hom.FP64, hom.MIXED):
+        st = hom.track(h, csys.c, z0, -32.0, hom.default_params(prec))
+        s = _np(st.status)
+        ok = s == 0
+        say(f"  prec {prec}: ok {ok.mean():.5f} evals/path {_np(st.counters)[:, 3].mean():.1f}")
+        assert ok.mean() >= 0.999
+        z = _np(st.z)[ok]
+        assert len(_key(z)) == len(z)
+        assert oracle.residual(csys, csys.c, z).max() <= 1e-10
+
+
+def test_resume_bitwise(hom):
+    say("[track resume] c5 P=256")
+    csys, cell, z0 = W.planted_config("c5", P=256)
+    h = hom.System.from_workload(csys)
+    full = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64))
+    p = hom.default_params(hom.FP64, max_steps=9)
+    st = hom.track(h, csys.c, z0, -32.0, p)
+    for _ in range(500):
+        if not (_np(st.status) == hom.PATH_RUNNING).any():
+            break
+        st = hom.track(h, csys.c, None, None, p, state=st)
+    assert np.array_equal(_np(st.z), _np(full.z)) and np.array_equal(_np(st.s), _np(full.s))
+    assert np.array_equal(_np(st.status), _np(full.status))
+
+
+def test_deterministic_and_batch_independent(hom):
+    """Bitwise-equal endpoints across runs and when the path set is split."""
+    say("[track determinism] c5 P=300")
+    csys, cell, z0 = W.planted_config("c5", P=300)
+    h = hom.System.from_workload(csys)
+    a = hom.track(h, csys.c, z0, -32.0)
+    b = hom.track(h, csys.c, z0, -32.0)
+    c1 = hom.track(h, csys.c, z0[:117], -32.0)
+    c2 = hom.track(h, csys.c, z0[117:], -32.0)
+    assert np.array_equal(_np(a.z), _np(b.z))
+    assert np.array_equal(_np(a.z), np.concatenate([_np(c1.z), _np(c2.z)]))
+
+
+def test_failure_modes_forced(hom):
+    """Host-forced outcomes on the GPU match the oracle's: a start point far off every path, a
+    NaN start, a zero step budget."""
+    say("[track failures] c5 P=8")
+    csys, cell, z0 = W.planted_config("c5", P=8)
+    bad = z0.copy()
+    bad[0] += 0.7
+    bad[1, 0] = np.nan
+    h = hom.System.from_workload(csys)
+    st = hom.track(h, csys.c, bad, -32.0)
+    _, _, _, ost, _ = oracle.track(csys, csys.c, bad, -32.0)
+    assert np.array_equal(_np(st.status), ost)
+    st = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64, max_steps=0))
+    assert (_np(st.status) == hom.PATH_RUNNING).all() and (_np(st.s) == -32.0).all()
+    st = hom.track(h, csys.c, z0[:0], -32.0)  # P = 0
+    assert st.z.shape[0] == 0
