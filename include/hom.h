@@ -126,7 +126,13 @@ typedef struct {
     int32_t max_steps;  /* accepted steps per call; then HOM_PATH_RUNNING */
     int32_t max_iters;  /* eval+solve cap per path per call; then HOM_PATH_MAX_ITERS */
     int32_t precision;  /* HOM_FP64 or HOM_MIXED */
+    int32_t flags;      /* 0 or HOM_TRACK_EXACT_SHIFT */
 } hom_track_params;
+
+/* hom_track_params.flags: recompute every row's maximum (the e^{-M_k} row shift) at every
+ * evaluation instead of reusing the previous evaluation's maximum.  Slower (one more pass over
+ * the monomials); makes a resumed run bitwise equal to an uninterrupted one. */
+#define HOM_TRACK_EXACT_SHIFT 1
 
 /* Fill `p` with this library's defaults for `precision`. */
 int hom_track_params_default(hom_track_params *p, int precision);
@@ -143,8 +149,9 @@ int hom_track_params_default(hom_track_params *p, int precision);
  * eval+solves.  sys_idx must be NULL (single-system handle).
  * With precision HOM_MIXED the steps run in the mixed form and every path that reaches s = 0
  * finishes with an FP64 endgame; paths the mixed form fails are re-tracked in FP64.
- * Resume is bitwise: calling with max_steps = k until no path is RUNNING gives the same z and
- * s as one call (the counters then include one extra eval+solve per resume).
+ * Resume: calling with max_steps = k until no path is RUNNING gives the same endpoints as one
+ * call; bitwise the same z and s with HOM_TRACK_EXACT_SHIFT (the counters then include one extra
+ * eval+solve per resume), equal to rounding otherwise (the row shifts differ after a resume).
  */
 int hom_track(hom_system_t sys, const double *c, int64_t P, double *z, double *s, double *ds,
               const int32_t *sys_idx, const hom_track_params *params, int32_t *status,

@@ -28,6 +28,7 @@ UNSCALED, AFFINE, EVAL_FP32 = 1, 2, 4
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
+TRACK_EXACT_SHIFT = 1
 
 EXPORTED = ["hom_create", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_track_params_default", "hom_track", "hom_endpoint_grad", "hom_set_profiling",
@@ -47,7 +48,8 @@ class TrackParams(ctypes.Structure):
                 ("div_re", ctypes.c_double), ("sing_ratio", ctypes.c_double),
                 ("max_polish", ctypes.c_int32), ("max_newton", ctypes.c_int32),
                 ("max_end", ctypes.c_int32), ("max_steps", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 def _load():

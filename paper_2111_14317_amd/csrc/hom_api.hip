@@ -312,13 +312,15 @@ int hom_track_params_default(hom_track_params *p, int precision) {
   p->max_steps = 100000;
   p->max_iters = 100000;
   p->precision = precision;
+  p->flags = 0;
   return HOM_OK;
 }
 
 static TrackDev to_dev(const hom_track_params *p) {
   return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
                   p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
-                  p->max_newton, p->max_end,    p->max_steps, p->max_iters};
+                  p->max_newton, p->max_end,    p->max_steps, p->max_iters,
+                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0};
 }
 
 // restore failed mixed-form paths to their start (z, s) and mark them fresh for the FP64 pass
@@ -349,7 +351,7 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     HOM_FAIL(HOM_EINVAL, "hom_track: bad precision");
   if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
       params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
-      params->max_steps < 0 || params->max_iters < 1)
+      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~HOM_TRACK_EXACT_SHIFT))
     HOM_FAIL(HOM_EINVAL, "hom_track: bad params");
   if (P == 0) return HOM_OK;
   if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, "hom_track: NULL array");

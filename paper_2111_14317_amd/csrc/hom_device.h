@@ -12,8 +12,9 @@
 //    lane-local: no cross-lane traffic during the evaluation.
 //  * lu_solve2  (A5, Sec. 6 in its affine form): LU with partial pivoting of J_z on the augmented
 //    rows, both right-hand sides (H_s, H) at once.  Rows stay in registers; the pivot search is a
-//    rotation-doubling argmax across the group and the pivot row is broadcast with ds_bpermute.
-//    Back substitution is column oriented, so every solution entry is broadcast once.
+//    rotation-doubling max of packed (magnitude, row) keys across the group and the pivot row is
+//    broadcast with ds_bpermute.  Back substitution is column oriented, so every solution entry
+//    is broadcast once.
 //
 // The exponent table in LDS is laid out [i][r][LD] (monomial, equation, exponent) with the
 // lifting w in slot N and LD odd, so the n lanes of a group reading monomial i of their own
@@ -86,23 +87,28 @@ struct Geo {
   }
 };
 
-// Group-wide argmax of (mag, idx) with ties to the lowest idx, by rotation doubling: after the
-// step with offset o every lane holds the best of the window [r, r + 2o) (mod N).  Max is
-// idempotent, so windows wrapping onto themselves are harmless.  Every lane of the wave must
-// execute this (the shuffles read other lanes).
-template <int N, typename T>
-__device__ __forceinline__ void group_argmax(T &mag, int &idx, int r, int base) {
+// Pivot-search key: the top 32 bits of a non-negative magnitude (monotone in the value), with the
+// low 6 bits replaced by 63 - r, so that an unsigned max over the group returns the largest
+// magnitude (to ~14 significant bits) and, among equal keys, the lowest row.  Rows already used
+// as pivots get key 0, below every candidate.
+__device__ __forceinline__ uint32_t pivot_key(double mag, int r) {
+  const uint32_t hi = (uint32_t)(__double_as_longlong(mag) >> 32);
+  return (hi & ~63u) | (uint32_t)(63 - r);
+}
+__device__ __forceinline__ uint32_t pivot_key(float mag, int r) {
+  return ((uint32_t)__float_as_uint(mag) & ~63u) | (uint32_t)(63 - r);
+}
+
+template <int N>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t v, int r, int base) {
 #pragma unroll
   for (int off = 1; off < N; off <<= 1) {
     int t = r + off;
     t = t >= N ? t - N : t;
-    const int src = base + t;
-    const T om = __shfl(mag, src, 64);
-    const int oi = __shfl(idx, src, 64);
-    const bool take = (om > mag) || (om == mag && oi < idx);
-    mag = take ? om : mag;
-    idx = take ? oi : idx;
+    const uint32_t o = (uint32_t)__shfl((int)v, base + t, 64);
+    v = o > v ? o : v;
   }
+  return v;
 }
 
 // Maximum over the group (every lane ends with it); NaN propagates.
@@ -178,10 +184,22 @@ __device__ SysLds<N> stage_tables(char *smem, const SysDev &sd, const double *__
 // row[j], j < N: dh_r/dz_j;  row[N]: dh_r/ds;  row[N+1]: h_r.  logM = M_r; absum = sum |V_i|.
 // T is the precision of the exponentials and of the contraction (double, or float for the
 // mixed form).  The exponent sums u are always formed in FP64.
+//
+// Row shift.  With `exact` the shift is the row maximum of Re u (a first pass over the
+// monomials).  Otherwise the shift is the caller's `Mlag` (the previous evaluation's maximum at a
+// nearby point); the exact maximum of this evaluation is returned in `Mlag` either way.  Any shift
+// gives the same directions (row scaling), so the lag only has to keep the terms in range: the
+// function returns false when the maximum moved further than the type's safe margin, and the
+// caller must then discard the row and evaluate again with `exact`.
+template <typename T>
+struct ShiftMargin {
+  static constexpr double value = sizeof(T) == 8 ? 300.0 : 40.0;
+};
+
 template <int N, typename T>
-__device__ __forceinline__ void eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
+__device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
                                          const double (&zi)[N], double s, Cx<T> (&row)[N + 2],
-                                         double &logM, T &absum) {
+                                         double &logM, T &absum, double &Mlag, bool exact) {
   constexpr int LD = TableLD<N>::value;
 #pragma unroll
   for (int j = 0; j < N + 2; ++j) row[j] = {T(0), T(0)};
@@ -192,20 +210,23 @@ __device__ __forceinline__ void eval_row(const SysLds<N> &S, int r, const double
     for (int j = 0; j < N; ++j)
       if (j == r) row[j].x = T(1);
     absum = T(1);
-    return;
+    return true;
   }
   const int n = S.n, mr = S.mk[r];
-  // pass 1: row maximum of Re u
-  double M = -INFINITY;
+  double M = Mlag;
+  if (exact) {  // pass 1: row maximum of Re u
+    M = -INFINITY;
 #pragma unroll 1
-  for (int i = 0; i < mr; ++i) {
-    const double *t = S.T + (i * n + r) * LD;
-    double e = t[N] * s;
+    for (int i = 0; i < mr; ++i) {
+      const double *t = S.T + (i * n + r) * LD;
+      double e = t[N] * s;
 #pragma unroll
-    for (int j = 0; j < N; ++j) e = fma(t[j], zr[j], e);
-    M = fmax(M, e);
+      for (int j = 0; j < N; ++j) e = fma(t[j], zr[j], e);
+      M = fmax(M, e);
+    }
   }
   logM = M;
+  double Mnew = -INFINITY;
   // pass 2: shifted exponentials and the contraction with [a | w | 1]
 #pragma unroll 1
   for (int i = 0; i < mr; ++i) {
@@ -216,6 +237,7 @@ __device__ __forceinline__ void eval_row(const SysLds<N> &S, int r, const double
       re = fma(t[j], zr[j], re);
       im = fma(t[j], zi[j], im);
     }
+    Mnew = fmax(Mnew, re);
     double turns = im * kInv2Pi;
     turns -= rint(turns);  // phase in turns, [-1/2, 1/2]
     const Cx<double> cc = S.C[i * n + r];
@@ -249,6 +271,20 @@ __device__ __forceinline__ void eval_row(const SysLds<N> &S, int r, const double
     row[N + 1].x += v.x;
     row[N + 1].y += v.y;
   }
+  Mlag = Mnew;
+  // an exact shift is always accepted (also when NaN inputs make every sum NaN), so a caller that
+  // retries with `exact` cannot loop
+  const double d = Mnew - M;
+  return exact || (d <= ShiftMargin<T>::value && d >= -ShiftMargin<T>::value);
+}
+
+// One evaluation with the exact row maximum as the shift.
+template <int N, typename T>
+__device__ __forceinline__ void eval_row_exact(const SysLds<N> &S, int r, const double (&zr)[N],
+                                               const double (&zi)[N], double s,
+                                               Cx<T> (&row)[N + 2], double &logM, T &absum) {
+  double Ml = 0.0;
+  eval_row<N, T>(S, r, zr, zi, s, row, logM, absum, Ml, true);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -269,12 +305,14 @@ __device__ __forceinline__ bool lu_solve2(Cx<T> (&row)[N + 2], int r, int base, 
   bool sing = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    T mag = used ? T(-1) : (row[j].x * row[j].x + row[j].y * row[j].y);
-    int idx = r;
-    group_argmax<N, T>(mag, idx, r, base);
+    const T mine = row[j].x * row[j].x + row[j].y * row[j].y;
+    uint32_t key = used ? 0u : pivot_key(mine, r);
+    key = group_max_u32<N>(key, r, base);
+    const int idx = 63 - (int)(key & 63u);
     pl[j] = idx;
     const int src = base + idx;
     const Cx<T> pv = shfl_cx(row[j], src);
+    const T mag = pv.x * pv.x + pv.y * pv.y;
     sing |= !(mag > T(0) && mag < T(INFINITY));
     if (j < n) {
       pmin2 = fmin(pmin2, mag);

@@ -30,6 +30,7 @@ struct System {
 struct TrackDev {
   double ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re, sing_ratio;
   int max_polish, max_newton, max_end, max_steps, max_iters;
+  int exact_shift;
 };
 
 // internal path statuses between the mixed pass and the FP64 pass of one hom_track call:

@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_eval(SysDev sd, const double *__rest
     Cx<T> row[N + 2];
     double M;
     T absum;
-    eval_row<N, T>(S, r, zr, zi, sp, row, M, absum);
+    eval_row_exact<N, T>(S, r, zr, zi, sp, row, M, absum);
     if (r >= n) continue;
     const double scale = (flags & 1) ? exp(M) : 1.0;  // HOM_UNSCALED
     double *Gr = G + 2 * ((p * n + r) * (n + 2));
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__rest
     if constexpr (MIXED) {
       Cx<float> row[N + 2], ef, qf;
       float absum, rf;
-      eval_row<N, float>(S, r, zr, zi, sp, row, M, absum);
+      eval_row_exact<N, float>(S, r, zr, zi, sp, row, M, absum);
       sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
       e = {ef.x, ef.y};
       q = {qf.x, qf.y};
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__rest
       if (__any(redo)) {
         Cx<double> rowd[N + 2], ed, qd;
         double ad, rd, nEd, nNd;
-        eval_row<N, double>(S, r, zr, zi, sp, rowd, M, ad);
+        eval_row_exact<N, double>(S, r, zr, zi, sp, rowd, M, ad);
         const bool sd2 = lu_solve2<N, double>(rowd, r, geo.base, n, ed, qd, nEd, nNd, rd);
         if (redo) {
           e = ed;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__rest
     } else {
       Cx<double> row[N + 2];
       double absum;
-      eval_row<N, double>(S, r, zr, zi, sp, row, M, absum);
+      eval_row_exact<N, double>(S, r, zr, zi, sp, row, M, absum);
       sing = lu_solve2<N, double>(row, r, geo.base, n, e, q, nE, nN, ratio);
     }
     if (act) {

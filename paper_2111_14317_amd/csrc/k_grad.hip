@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__re
   Cx<T> row[N + 2];
   double Mr;
   T absum;
-  eval_row<N, T>(S, r, zr, zi, 0.0, row, Mr, absum);
+  eval_row_exact<N, T>(S, r, zr, zi, 0.0, row, Mr, absum);
   // transpose J_z through LDS: lane j takes conj of column j
   if (geo.valid) {
 #pragma unroll

@@ -65,6 +65,8 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
   int64_t path = -1;
   int phase = PH_POLISH, k = 0, steps_here = 0, iters = 0;
   bool has_acc = false;  // the slot's path has an accepted point (sZa, sEa, sa valid)
+  bool need_exact = true;  // next evaluation recomputes the row maximum (fresh path, lost lag)
+  double Mlag = 0.0;       // this lane's row maximum from the previous evaluation
   int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   bool exhausted = !geo.valid;
 #pragma unroll
@@ -78,14 +80,19 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       if (need && r == 0) cl = atomicAdd(queue, 1ull);
       cl = __shfl(cl, geo.base, 64);
       if (need) {
-        if ((int64_t)cl >= P) {
+        // claims [0, P) take paths with a full or partial track ahead (fresh, resumed, handed
+        // over from the mixed form); claims [P, 2P) take the short pending endgames, so that the
+        // few long paths start first instead of forming the tail of the launch
+        const int64_t lim = MIXED ? P : 2 * P;
+        if ((int64_t)cl >= lim) {
           exhausted = true;
           need = false;
         } else {
-          const int64_t p = (int64_t)cl;
+          const bool second = (int64_t)cl >= P;
+          const int64_t p = second ? (int64_t)cl - P : (int64_t)cl;
           const int st = status[p];
-          const bool fresh = st == 1, pend = st == kPendingEnd;
-          const bool resume = st == 2 || (st == kHandoff && !MIXED);
+          const bool fresh = !second && st == 1, pend = second && st == kPendingEnd;
+          const bool resume = !second && (st == 2 || (st == kHandoff && !MIXED));
           if ((fresh || resume) || (pend && !MIXED)) {
             path = p;
             need = false;
@@ -105,6 +112,7 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
             iters = 0;
             nrm_prev = 0.0;
             has_acc = false;
+            need_exact = true;  // also always true with pr.exact_shift
             c0 = counters[4 * p];
             c1 = counters[4 * p + 1];
             c2 = counters[4 * p + 2];
@@ -119,13 +127,13 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
     // ---- one evaluation + consolidated solve (every lane) ----
     double nE, nN, resid, ratio;
     Cx<double> e, q;
-    bool sing;
+    bool sing, shift_ok;
     {
       double M;
       if constexpr (MIXED) {
         Cx<float> row[N + 2], ef, qf;
         float absum, rf;
-        eval_row<N, float>(S, r, zr, zi, sc, row, M, absum);
+        shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Mlag, need_exact);
         const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
         sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
         resid = group_max<N, double>((double)h2, r, geo.base);  // squared
@@ -135,12 +143,14 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       } else {
         Cx<double> row[N + 2];
         double absum;
-        eval_row<N, double>(S, r, zr, zi, sc, row, M, absum);
+        shift_ok = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Mlag, need_exact);
         const double h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
         sing = lu_solve2<N, double>(row, r, geo.base, n, e, q, nE, nN, ratio);
         resid = group_max<N, double>(h2, r, geo.base);  // squared relative residual
       }
     }
+    // every lane of the group must have kept its terms in range, else redo with exact shifts
+    const bool group_shift_ok = group_max_u32<N>(shift_ok ? 0u : 1u, r, geo.base) == 0u;
     if (geo.valid) {  // lanes past the last full group own no slot
       sEc[r] = e;
       sNc[r] = q;
@@ -149,6 +159,8 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
     __builtin_amdgcn_wave_barrier();
 
     if (!active) continue;
+    need_exact = !group_shift_ok || pr.exact_shift;
+    if (!group_shift_ok) continue;  // discard this evaluation; the next one uses exact shifts
 
     // ---- scalar update of the slot (divergent across groups, identical within a group) ----
     bool fin = false;
