@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--paths", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 512 MiB device-to-device copy (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
@@ -138,6 +140,14 @@ def main():
     import paper_2111_14317_amd as hom
     csys, z0 = _workload(args.paths)
     h = hom.System.from_workload(csys)
+    if args.copy_calib:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = {}
     for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
         res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup)

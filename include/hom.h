@@ -76,11 +76,29 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
 int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int flags,
                hom_system_t *out);
 
+/* One system of a batch: n unknowns, m [n], A [M][n] int8 (equation-major), w [M] (host). */
+typedef struct {
+    int32_t n;
+    const int32_t *m;
+    const int8_t *A;
+    const double *w;
+} hom_sys_desc;
+
+/*
+ * Create a handle over several systems of uneven n and support sizes (the batched form), tracked
+ * together by one persistent launch of hom_track.  Each system is validated as in hom_create;
+ * num_sys in [1, 65536].  Systems whose tables do not fit the LDS budget are read from global
+ * memory.  Only hom_track accepts batch handles (the other compute calls return
+ * HOM_EUNSUPPORTED).  Synchronous.  flags must be 0.
+ */
+int hom_create_batch(int num_sys, const hom_sys_desc *descs, int flags, hom_system_t *out);
+
 /* Release a handle (waits for the device).  NULL is accepted. */
 int hom_destroy(hom_system_t sys);
 
-/* n, M and the largest m_k of a handle (any pointer may be NULL). */
-int hom_system_info(hom_system_t sys, int *n, int64_t *M, int *m_max);
+/* n (the largest n of a batch), M (total over a batch), the largest m_k and the number of
+ * systems of a handle (any pointer may be NULL). */
+int hom_system_info(hom_system_t sys, int *n, int64_t *M, int *m_max, int *num_sys);
 
 /*
  * Evaluate the extended Jacobian [J_z | H_s | H] at P points (Sec. 5.1 and 5.2; Sec. 7, Alg. 2):
@@ -127,6 +145,8 @@ typedef struct {
     int32_t max_iters;  /* eval+solve cap per path per call; then HOM_PATH_MAX_ITERS */
     int32_t precision;  /* HOM_FP64 or HOM_MIXED */
     int32_t flags;      /* 0 or HOM_TRACK_EXACT_SHIFT */
+    int32_t tile;       /* batched form: paths per work item = tile x lane groups per block
+                           (0: the default, 4) */
 } hom_track_params;
 
 /* hom_track_params.flags: recompute every row's maximum (the e^{-M_k} row shift) at every
@@ -146,9 +166,16 @@ int hom_track_params_default(hom_track_params *p, int precision);
  * status: int32 [P] in/out: HOM_PATH_START (fresh) or HOM_PATH_RUNNING (resume); other values
  * are left untouched and the path is skipped.
  * counters: int32 [P][4] accumulated: accepted steps, rejected steps, corrector iterations,
- * eval+solves.  sys_idx must be NULL (single-system handle).
- * With precision HOM_MIXED the steps run in the mixed form and every path that reaches s = 0
- * finishes with an FP64 endgame; paths the mixed form fails are re-tracked in FP64.
+ * eval+solves.  sys_idx must be NULL for a single-system handle.
+ * Batch handle (hom_create_batch): c is the concatenation of the systems' coefficient arrays
+ * (complex128 [sum of M]); z is complex128 [P][n_max] (path p uses its first n of its system);
+ * sys_idx int32 [P] gives each path's system, non-decreasing (each system's paths contiguous),
+ * values in [0, num_sys).  Work items are (system, run of consecutive paths); a block stages the
+ * system's tables and its lane groups (sized for that system's n) claim the item's paths.
+ * With precision HOM_MIXED the evaluations and solves run in FP32 (exponent sums, state and
+ * decisions in FP64); a path evaluates in FP64 to polish its start point and for its endgame at
+ * s = 0, after a failed FP32 evaluation (until its next accepted point), and for the rest of its
+ * track once 3 consecutive steps were rejected.
  * Resume: calling with max_steps = k until no path is RUNNING gives the same endpoints as one
  * call; bitwise the same z and s with HOM_TRACK_EXACT_SHIFT (the counters then include one extra
  * eval+solve per resume), equal to rounding otherwise (the row shifts differ after a resume).

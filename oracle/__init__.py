@@ -123,7 +123,7 @@ class TrackParams:
     res_tol: float = 1e-10
     div_re: float = 40.0
     sing_ratio: float = 1e-14
-    max_polish: int = 5
+    max_polish: int = 10
     max_newton: int = 3
     max_end: int = 8
     max_steps: int = 100000

@@ -30,7 +30,7 @@ PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
 TRACK_EXACT_SHIFT = 1
 
-EXPORTED = ["hom_create", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
+EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_track_params_default", "hom_track", "hom_endpoint_grad", "hom_set_profiling",
             "hom_profile_read", "hom_last_error"]
 
@@ -49,7 +49,12 @@ class TrackParams(ctypes.Structure):
                 ("max_polish", ctypes.c_int32), ("max_newton", ctypes.c_int32),
                 ("max_end", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+class SysDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_void_p), ("A", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
 
 
 def _load():
@@ -59,8 +64,9 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     lib.hom_create.argtypes = [i32, P, P, P, i32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.hom_create_batch.argtypes = [i32, P, i32, ctypes.POINTER(ctypes.c_void_p)]
     lib.hom_destroy.argtypes = [P]
-    lib.hom_system_info.argtypes = [P, P, P, P]
+    lib.hom_system_info.argtypes = [P, P, P, P, P]
     lib.hom_eval.argtypes = [P, P, i64, P, P, P, P, i32, P]
     lib.hom_step.argtypes = [P, P, i64, P, P, P, P, P, i32, P]
     lib.hom_track_params_default.argtypes = [ctypes.POINTER(TrackParams), i32]
@@ -105,6 +111,8 @@ def default_params(precision=FP64, **overrides) -> TrackParams:
 class System:
     """A system handle (Alg. 1): exponents A int8 [M][n] equation-major, liftings w [M]."""
 
+    num_sys = 1
+
     def __init__(self, n, m, A, w):
         m = np.ascontiguousarray(m, np.int32)
         A = np.ascontiguousarray(A, np.int8)
@@ -131,6 +139,30 @@ class System:
             self.close()
         except Exception:
             pass
+
+
+class Batch(System):
+    """A handle over several systems of uneven n and supports (the batched form): only `track`
+    accepts it, with paths grouped by system (see `track`)."""
+
+    def __init__(self, systems):
+        keep, descs = [], (SysDesc * len(systems))()
+        ns = []
+        for q, sy in enumerate(systems):
+            m = np.ascontiguousarray(sy.m, np.int32)
+            A = np.ascontiguousarray(sy.A, np.int8)
+            w = np.ascontiguousarray(sy.w, np.float64)
+            keep += [m, A, w]
+            descs[q] = SysDesc(int(sy.n), m.ctypes.data, A.ctypes.data, w.ctypes.data)
+            ns.append(int(sy.n))
+        h = ctypes.c_void_p()
+        _check(lib.hom_create_batch(len(systems), descs, 0, ctypes.byref(h)))
+        del keep
+        self.handle = h
+        self.n = max(ns)
+        self.ns = ns
+        self.num_sys = len(systems)
+        self.M = int(sum(int(np.sum(sy.m)) for sy in systems))
 
 
 def _dev_like(x, dtype, device):
@@ -179,11 +211,19 @@ class TrackState:
 
 
 def track(sys: System, c, z0, s0, params: TrackParams | None = None, state: TrackState | None = None,
-          device="cuda") -> TrackState:
-    """Track paths to s = 0.  Pass `state` (from a previous call) to resume RUNNING paths."""
+          device="cuda", sys_idx=None) -> TrackState:
+    """Track paths to s = 0.  Pass `state` (from a previous call) to resume RUNNING paths.
+    Batch handle: c is the concatenation of the systems' coefficients, z0 is [P][n_max] (each
+    path uses the first n of its system), sys_idx [P] int32 non-decreasing."""
     import torch
     params = params or default_params()
     c = _dev_like(c, torch.complex128, device)
+    if sys.num_sys > 1 or isinstance(sys, Batch):
+        if sys_idx is None:
+            raise ValueError("a batch handle needs sys_idx")
+        sys_idx = _dev_like(sys_idx, torch.int32, device)
+    elif sys_idx is not None:
+        raise ValueError("sys_idx is only for batch handles")
     if state is None:
         z = _dev_like(z0, torch.complex128, device).reshape(-1, sys.n).clone()
         P = z.shape[0]
@@ -193,8 +233,9 @@ def track(sys: System, c, z0, s0, params: TrackParams | None = None, state: Trac
                            torch.full((P,), PATH_START, dtype=torch.int32, device=device),
                            torch.zeros((P, 4), dtype=torch.int32, device=device))
     P = state.z.shape[0]
-    _check(lib.hom_track(sys.handle, _ptr(c), P, _ptr(state.z), _ptr(state.s), _ptr(state.ds), None,
-                         ctypes.byref(params), _ptr(state.status), _ptr(state.counters), _stream()))
+    _check(lib.hom_track(sys.handle, _ptr(c), P, _ptr(state.z), _ptr(state.s), _ptr(state.ds),
+                         _ptr(sys_idx), ctypes.byref(params), _ptr(state.status),
+                         _ptr(state.counters), _stream()))
     return state
 
 

@@ -1,6 +1,8 @@
 // C ABI (include/hom.h): argument validation, handles, workspaces, launches.
 #include <string.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -121,6 +123,58 @@ struct hom_system_s {
 
 static constexpr size_t kMaxLds = 48 * 1024;  // leaves room for per-group state
 
+// Validate one system; fills M and the largest m_k.  Returns an empty string or the problem.
+static std::string validate_system(int n, const int32_t *m, const int8_t *A, const double *w,
+                                   int64_t *M_out, int *mmax_out) {
+  if (n < 1 || n > 32) return "n must be in [1, 32]";
+  if (!m || !A || !w) return "m, A and w must be non-NULL";
+  int64_t M = 0;
+  int mmax = 0;
+  for (int k = 0; k < n; ++k) {
+    if (m[k] < 1) return "every m[k] must be >= 1";
+    M += m[k];
+    if (m[k] > mmax) mmax = m[k];
+  }
+  if (M > 65536) return "M must be <= 65536";
+  for (int64_t i = 0; i < M * n; ++i)
+    if (A[i] == -128) return "exponents must lie in [-127, 127]";
+  for (int64_t i = 0; i < M; ++i)
+    if (!std::isfinite(w[i]) || w[i] < 0) return "liftings must be finite and non-negative";
+  *M_out = M;
+  *mmax_out = mmax;
+  return "";
+}
+
+// Exponent table [mmax][n][LD]: exponents as doubles zero padded to N, lifting in slot N.
+static void build_table(int n, int N, const int32_t *m, const int8_t *A, const double *w, int mmax,
+                        std::vector<double> &T, std::vector<int32_t> &off) {
+  const int LD = table_ld(N);
+  off.assign(n, 0);
+  int64_t acc = 0;
+  for (int k = 0; k < n; ++k) {
+    off[k] = (int32_t)acc;
+    acc += m[k];
+  }
+  T.assign((size_t)mmax * n * LD, 0.0);
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < m[k]; ++i) {
+      double *t = &T[((size_t)i * n + k) * LD];
+      const int8_t *a = A + (size_t)(off[k] + i) * n;
+      for (int j = 0; j < n; ++j) t[j] = (double)a[j];
+      t[N] = w[off[k] + i];
+    }
+}
+
+static void free_system(System &S) {
+  hipFree(S.dT);
+  hipFree(S.dmk);
+  hipFree(S.doff);
+  hipFree(S.dA);
+  hipFree(S.dBatch);
+  hipFree(S.dT_all);
+  hipFree(S.dInts_all);
+}
+
 extern "C" {
 
 const char *hom_last_error(void) { return g_err.c_str(); }
@@ -169,42 +223,19 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   g_err.clear();
   if (!out) HOM_FAIL(HOM_EINVAL, "hom_create: out is NULL");
   *out = nullptr;
-  if (n < 1 || n > 32) HOM_FAIL(HOM_EINVAL, "hom_create: n must be in [1, 32]");
-  if (!m || !A || !w) HOM_FAIL(HOM_EINVAL, "hom_create: m, A and w must be non-NULL");
   if (flags != 0) HOM_FAIL(HOM_EINVAL, "hom_create: flags must be 0");
   int64_t M = 0;
   int mmax = 0;
-  for (int k = 0; k < n; ++k) {
-    if (m[k] < 1) HOM_FAIL(HOM_EINVAL, "hom_create: every m[k] must be >= 1");
-    M += m[k];
-    if (m[k] > mmax) mmax = m[k];
-  }
-  if (M > 65536) HOM_FAIL(HOM_EINVAL, "hom_create: M must be <= 65536");
-  for (int64_t i = 0; i < M * n; ++i)
-    if (A[i] == -128) HOM_FAIL(HOM_EINVAL, "hom_create: exponents must lie in [-127, 127]");
-  for (int64_t i = 0; i < M; ++i)
-    if (!std::isfinite(w[i]) || w[i] < 0)
-      HOM_FAIL(HOM_EINVAL, "hom_create: liftings must be finite and non-negative");
+  const std::string bad = validate_system(n, m, A, w, &M, &mmax);
+  if (!bad.empty()) HOM_FAIL(HOM_EINVAL, "hom_create: " + bad);
   const int N = bucket_for(n);
   const size_t lds = lds_for(N, n, mmax);
   if (lds > kMaxLds)
     HOM_FAIL(HOM_EUNSUPPORTED, "hom_create: system tables exceed the LDS budget (" +
-                                   std::to_string(lds) + " bytes)");
-  const int LD = table_ld(N);
-  std::vector<int32_t> off(n);
-  int64_t acc = 0;
-  for (int k = 0; k < n; ++k) {
-    off[k] = (int32_t)acc;
-    acc += m[k];
-  }
-  std::vector<double> T((size_t)mmax * n * LD, 0.0);
-  for (int k = 0; k < n; ++k)
-    for (int i = 0; i < m[k]; ++i) {
-      double *t = &T[((size_t)i * n + k) * LD];
-      const int8_t *a = A + (size_t)(off[k] + i) * n;
-      for (int j = 0; j < n; ++j) t[j] = (double)a[j];
-      t[N] = w[off[k] + i];
-    }
+                                   std::to_string(lds) + " bytes); use hom_create_batch");
+  std::vector<double> T;
+  std::vector<int32_t> off;
+  build_table(n, N, m, A, w, mmax, T, off);
   std::vector<int32_t> A32((size_t)M * n);
   for (size_t i = 0; i < A32.size(); ++i) A32[i] = A[i];
 
@@ -217,10 +248,7 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   S.lds_bytes = lds;
   auto fail = [&](hipError_t e, const char *what) {
     set_error(std::string("hom_create: ") + what + ": " + hipGetErrorString(e));
-    hipFree(S.dT);
-    hipFree(S.dmk);
-    hipFree(S.doff);
-    hipFree(S.dA);
+    free_system(S);
     delete h;
     return e == hipErrorOutOfMemory ? HOM_ENOMEM : HOM_EDEVICE;
   };
@@ -242,24 +270,102 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   return HOM_OK;
 }
 
+int hom_create_batch(int num_sys, const hom_sys_desc *descs, int flags, hom_system_t *out) {
+  g_err.clear();
+  if (!out) HOM_FAIL(HOM_EINVAL, "hom_create_batch: out is NULL");
+  *out = nullptr;
+  if (flags != 0) HOM_FAIL(HOM_EINVAL, "hom_create_batch: flags must be 0");
+  if (num_sys < 1 || num_sys > 65536 || !descs)
+    HOM_FAIL(HOM_EINVAL, "hom_create_batch: num_sys must be in [1, 65536] with descs non-NULL");
+  std::vector<BatchSysDev> info(num_sys);
+  std::vector<double> T_all;
+  std::vector<int32_t> ints_all;
+  int64_t c_acc = 0, C_acc = 0;
+  int n_max = 0, mmax_all = 0;
+  size_t lds_max = 0;
+  for (int q = 0; q < num_sys; ++q) {
+    const hom_sys_desc &d = descs[q];
+    int64_t M = 0;
+    int mmax = 0;
+    const std::string bad = validate_system(d.n, d.m, d.A, d.w, &M, &mmax);
+    if (!bad.empty())
+      HOM_FAIL(HOM_EINVAL, "hom_create_batch: system " + std::to_string(q) + ": " + bad);
+    const int N = bucket_for(d.n);
+    std::vector<double> T;
+    std::vector<int32_t> off;
+    build_table(d.n, N, d.m, d.A, d.w, mmax, T, off);
+    const size_t lds = lds_for(N, d.n, mmax);
+    BatchSysDev &b = info[q];
+    b.n = d.n;
+    b.N = N;
+    b.mmax = mmax;
+    b.M = (int)M;
+    b.T_off = (int64_t)T_all.size();
+    b.ints_off = (int64_t)ints_all.size();
+    b.c_off = c_acc;
+    b.C_off = C_acc;
+    b.lds_bytes = lds <= kMaxLds ? (int)lds : 0;
+    b.pad = 0;
+    if (b.lds_bytes > 0 && lds > lds_max) lds_max = lds;
+    T_all.insert(T_all.end(), T.begin(), T.end());
+    ints_all.insert(ints_all.end(), d.m, d.m + d.n);
+    ints_all.insert(ints_all.end(), off.begin(), off.end());
+    c_acc += M;
+    C_acc += (int64_t)mmax * d.n;
+    if (d.n > n_max) n_max = d.n;
+    if (mmax > mmax_all) mmax_all = mmax;
+  }
+  hom_system_s *h = new hom_system_s();
+  System &S = h->s;
+  S.n = n_max;
+  S.N = bucket_for(n_max);
+  S.mmax = mmax_all;
+  S.M = (int)std::min<int64_t>(c_acc, INT32_MAX);
+  S.M_total = c_acc;
+  S.num_sys = num_sys;
+  S.C_total = C_acc;
+  S.batch_lds = lds_max;
+  auto fail = [&](hipError_t e, const char *what) {
+    set_error(std::string("hom_create_batch: ") + what + ": " + hipGetErrorString(e));
+    free_system(S);
+    delete h;
+    return e == hipErrorOutOfMemory ? HOM_ENOMEM : HOM_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&S.device)) != hipSuccess) return fail(e, "hipGetDevice");
+  if ((e = hipMalloc(&S.dBatch, info.size() * sizeof(BatchSysDev))) != hipSuccess)
+    return fail(e, "hipMalloc");
+  if ((e = hipMalloc(&S.dT_all, T_all.size() * 8)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMalloc(&S.dInts_all, ints_all.size() * 4)) != hipSuccess) return fail(e, "hipMalloc");
+  if ((e = hipMemcpy(S.dBatch, info.data(), info.size() * sizeof(BatchSysDev),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(S.dT_all, T_all.data(), T_all.size() * 8, hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail(e, "hipMemcpy");
+  if ((e = hipMemcpy(S.dInts_all, ints_all.data(), ints_all.size() * 4, hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail(e, "hipMemcpy");
+  *out = h;
+  return HOM_OK;
+}
+
 int hom_destroy(hom_system_t h) {
   g_err.clear();
   if (!h) return HOM_OK;
   hipDeviceSynchronize();
-  hipFree(h->s.dT);
-  hipFree(h->s.dmk);
-  hipFree(h->s.doff);
-  hipFree(h->s.dA);
+  free_system(h->s);
   delete h;
   return HOM_OK;
 }
 
-int hom_system_info(hom_system_t h, int *n, int64_t *M, int *m_max) {
+int hom_system_info(hom_system_t h, int *n, int64_t *M, int *m_max, int *num_sys) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_system_info: NULL handle");
   if (n) *n = h->s.n;
-  if (M) *M = h->s.M;
+  if (M) *M = h->s.num_sys > 0 ? h->s.M_total : h->s.M;
   if (m_max) *m_max = h->s.mmax;
+  if (num_sys) *num_sys = h->s.num_sys > 0 ? h->s.num_sys : 1;
   return HOM_OK;
 }
 
@@ -267,6 +373,7 @@ int hom_eval(hom_system_t h, const double *c, int64_t P, const double *z, const 
              double *G, double *logscale, int flags, hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL handle");
+  if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_eval: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_eval: P < 0");
   if (flags & ~7) HOM_FAIL(HOM_EINVAL, "hom_eval: unknown flags");
   if (P == 0) return HOM_OK;
@@ -280,6 +387,7 @@ int hom_step(hom_system_t h, const double *c, int64_t P, const double *z, const 
              hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_step: NULL handle");
+  if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_step: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_step: P < 0");
   if (precision != HOM_FP64 && precision != HOM_MIXED)
     HOM_FAIL(HOM_EINVAL, "hom_step: precision must be HOM_FP64 or HOM_MIXED");
@@ -306,13 +414,14 @@ int hom_track_params_default(hom_track_params *p, int precision) {
   p->res_tol = 1e-10;
   p->div_re = 40.0;
   p->sing_ratio = 1e-14;
-  p->max_polish = 5;
+  p->max_polish = 10;
   p->max_newton = 3;
   p->max_end = 8;
   p->max_steps = 100000;
   p->max_iters = 100000;
   p->precision = precision;
   p->flags = 0;
+  p->tile = 0;
   return HOM_OK;
 }
 
@@ -320,23 +429,7 @@ static TrackDev to_dev(const hom_track_params *p) {
   return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
                   p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
                   p->max_newton, p->max_end,    p->max_steps, p->max_iters,
-                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0};
-}
-
-// restore failed mixed-form paths to their start (z, s) and mark them fresh for the FP64 pass
-__global__ void k_restart_failed(int64_t P, int n, double *z, double *s, double *ds,
-                                 int32_t *status, const double *z0, const double *s0,
-                                 const double *ds0, const int32_t *st0) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const int st = status[p];
-  const int was = st0[p];
-  if (st < 0 && st != HOM_PATH_MAX_ITERS && (was == HOM_PATH_START || was == HOM_PATH_RUNNING)) {
-    for (int j = 0; j < 2 * n; ++j) z[2 * p * n + j] = z0[2 * p * n + j];
-    s[p] = s0[p];
-    ds[p] = ds0[p];
-    status[p] = was;
-  }
+                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile};
 }
 
 int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
@@ -346,44 +439,39 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_track: NULL handle");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_track: P < 0");
   if (!params) HOM_FAIL(HOM_EINVAL, "hom_track: NULL params");
-  if (sys_idx) HOM_FAIL(HOM_EINVAL, "hom_track: sys_idx must be NULL for a single-system handle");
+  const bool batch = h->s.num_sys > 0;
+  if (!batch && sys_idx)
+    HOM_FAIL(HOM_EINVAL, "hom_track: sys_idx must be NULL for a single-system handle");
+  if (batch && P > 0 && !sys_idx) HOM_FAIL(HOM_EINVAL, "hom_track: a batch handle needs sys_idx");
   if (params->precision != HOM_FP64 && params->precision != HOM_MIXED)
     HOM_FAIL(HOM_EINVAL, "hom_track: bad precision");
   if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
       params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
-      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~HOM_TRACK_EXACT_SHIFT))
+      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~HOM_TRACK_EXACT_SHIFT) ||
+      params->tile < 0)
     HOM_FAIL(HOM_EINVAL, "hom_track: bad params");
   if (P == 0) return HOM_OK;
   if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, "hom_track: NULL array");
   hipStream_t st = (hipStream_t)stream;
   const TrackDev pr = to_dev(params);
-  const int n = h->s.n;
-  // workspace: queue counter (+ in the mixed form, a copy of the start state)
-  size_t bytes = 256;
-  if (params->precision == HOM_MIXED) bytes += (size_t)P * (16 * n + 8 + 8 + 4) + 256;
-  char *ws = nullptr;
-  HOM_HIP(hipMallocAsync((void **)&ws, bytes, st), "hom_track: workspace");
-  unsigned long long *queue = reinterpret_cast<unsigned long long *>(ws);
   hipError_t e = hipSuccess;
-  if (params->precision == HOM_MIXED) {
-    double *z0 = reinterpret_cast<double *>(ws + 256);
-    double *s0 = z0 + 2 * P * n;
-    double *ds0 = s0 + P;
-    int32_t *st0 = reinterpret_cast<int32_t *>(ds0 + P);
-    e = hipMemcpyAsync(z0, z, (size_t)P * 16 * n, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s0, s, (size_t)P * 8, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(ds0, ds, (size_t)P * 8, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(st0, status, (size_t)P * 4, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, true, queue, st);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_restart_failed, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P,
-                         n, z, s, ds, status, z0, s0, ds0, st0);
-      e = hipGetLastError();
-    }
+  if (batch) {
+    // workspace: queue counter, per-system path and item offsets, table-order coefficients
+    void *ws = nullptr;
+    HOM_HIP(hipMallocAsync(&ws, track_batch_ws_bytes(h->s), st), "hom_track: workspace");
+    e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr,
+                           params->precision == HOM_MIXED, ws, st);
+    hipError_t e2 = hipFreeAsync(ws, st);
+    if (e != hipSuccess) HOM_HIP(e, "hom_track");
+    HOM_HIP(e2, "hom_track: free workspace");
+    return HOM_OK;
   }
-  // FP64 pass: the whole FP64 form, or the endgame and the fallbacks of the mixed form
-  if (e == hipSuccess) e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, false, queue, st);
-  hipError_t e2 = hipFreeAsync(ws, st);
+  // workspace: the device work-queue counter
+  unsigned long long *queue = nullptr;
+  HOM_HIP(hipMallocAsync((void **)&queue, 256, st), "hom_track: workspace");
+  e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, params->precision == HOM_MIXED,
+                   queue, st);
+  hipError_t e2 = hipFreeAsync(queue, st);
   if (e != hipSuccess) HOM_HIP(e, "hom_track");
   HOM_HIP(e2, "hom_track: free workspace");
   return HOM_OK;
@@ -393,6 +481,7 @@ int hom_endpoint_grad(hom_system_t h, const double *c, int64_t P, const double *
                       const double *grad_x, double *grad_c, int precision, hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: NULL handle");
+  if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_endpoint_grad: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: P < 0");
   if (precision != HOM_FP64 && precision != HOM_MIXED)
     HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: bad precision");

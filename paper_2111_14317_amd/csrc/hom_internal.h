@@ -15,8 +15,27 @@ constexpr int kSizes[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32};
 int bucket_for(int n);   // smallest compiled N >= n, or 0
 int table_ld(int N);     // TableLD<N>::value at run time
 
+// One system of a batch handle, as the batch kernel sees it.
+struct BatchSysDev {
+  int n, N, mmax, M;
+  int64_t T_off;     // offset (doubles) of the exponent table in the batch's table buffer
+  int64_t ints_off;  // offset of m_k [n] then the equation offsets [n] in the int buffer
+  int64_t c_off;     // first coefficient (complex index) in the concatenated c
+  int64_t C_off;     // offset of the table-order coefficients in the per-call workspace
+  int lds_bytes;     // LDS image of the tables, or 0 when they are read from global memory
+  int pad;
+};
+
 struct System {
   int n = 0, N = 0, mmax = 0, M = 0;
+  // batched form (num_sys > 0): n = largest n, M = total, mmax = largest m_k
+  int num_sys = 0;
+  BatchSysDev *dBatch = nullptr;     // device [num_sys]
+  double *dT_all = nullptr;          // device tables of all systems
+  int32_t *dInts_all = nullptr;      // device m_k and offsets of all systems
+  int64_t C_total = 0;               // table-order coefficient entries over all systems
+  int64_t M_total = 0;               // monomials over all systems
+  size_t batch_lds = 0;              // largest LDS image among the systems staged in LDS
   int device = 0;
   double *dT = nullptr;     // device [mmax][n][LD] exponent table + lifting
   int32_t *dmk = nullptr;   // device [n]
@@ -31,13 +50,9 @@ struct TrackDev {
   double ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re, sing_ratio;
   int max_polish, max_newton, max_end, max_steps, max_iters;
   int exact_shift;
+  int tile;
 };
 
-// internal path statuses between the mixed pass and the FP64 pass of one hom_track call:
-// reached s = 0 in the mixed form, FP64 endgame still to run
-constexpr int kPendingEnd = 3;
-// the mixed form failed after an accepted point: (z, s) is that point, continue in FP64
-constexpr int kHandoff = 4;
 
 void set_error(const std::string &msg);
 
@@ -58,6 +73,11 @@ hipError_t launch_step(const System &S, const double *c, int64_t P, const double
 hipError_t launch_track(const System &S, const double *c, int64_t P, double *z, double *s,
                         double *ds, int32_t *status, int32_t *counters, const TrackDev &pr,
                         bool mixed, unsigned long long *queue, hipStream_t stream);
+hipError_t launch_track_batch(const System &S, const double *c, int64_t P, double *z, double *s,
+                              double *ds, const int32_t *sys_idx, int32_t *status,
+                              int32_t *counters, const TrackDev &pr, bool mixed, void *ws,
+                              hipStream_t stream);
+size_t track_batch_ws_bytes(const System &S);
 hipError_t launch_grad(const System &S, const double *c, int64_t P, const double *z_end,
                        const double *grad_x, double *grad_c, int precision, double *work,
                        size_t work_elems, hipStream_t stream);

@@ -20,10 +20,10 @@
 // The CPU oracle runs the same rules with the same constants.
 //
 // Mixed form: the evaluation (exponentials, contraction) and the LU run in FP32; the exponent
-// sums, the state z, s and every decision stay FP64.  A path that reaches s = 0 stops with an
-// internal pending status and the FP64 launch that follows runs its endgame.  A path the mixed
-// form fails (e.g. pivots below FP32 resolution) continues in FP64 from its last accepted point,
-// or is re-tracked from its start when it failed before accepting any point.
+// sums, the state z, s and every decision stay FP64.  Per group, the evaluation runs in FP64 to
+// polish the start point and in the endgame, after an FP32 evaluation failed (until the next
+// accepted point), and for the rest of the path once kMixedFp64Rejects consecutive steps were
+// rejected, so one launch finishes every path.
 #include <stdio.h>
 
 #include "hom_internal.h"
@@ -35,38 +35,49 @@ constexpr int kTrackBlock = 256;
 enum : int { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
 enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_PREDICT = 2, ACT_END = 3 };
 
+// mixed form: after this many consecutive rejected steps a path evaluates in FP64 for the rest of
+// its track (the FP32 noise floor of the Newton step exceeds tol_track near ill-conditioned
+// points, and halving the step cannot fix that; switching back would only restart the cascade)
+constexpr int kMixedFp64Rejects = 3;
+
 template <int N>
 __host__ __device__ constexpr size_t track_state_bytes() {
   return (size_t)(kTrackBlock / 64) * Geo<N>::G * 4 * N * sizeof(Cx<double>);
 }
 
-// At most 256 registers per lane, so two waves share each SIMD (the FP64 form at n = 10 needs
-// slightly more than 256 without the bound and would run one wave per SIMD).
+// The tracker loop of one block's lane groups over the paths [p_begin, p_end) of one system.
+// Groups claim paths through `queue` (global memory for a whole launch, or LDS for one work item of
+// the batched form).  Path p's point is z[p * zstride + j], j < n.  slot_state: LDS for the
+// block's groups, 4 N complex values each.
 template <int N, bool MIXED>
-__global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_eu(2)))
-    k_track(SysDev sd, const double *__restrict__ c, int64_t P, double *__restrict__ z,
-            double *__restrict__ s, double *__restrict__ ds_io, int32_t *__restrict__ status,
-            int32_t *__restrict__ counters, TrackDev pr, unsigned long long *__restrict__ queue,
-            size_t table_bytes, unsigned long long *__restrict__ units) {
-  extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+__device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double> *slot_state,
+                                            int64_t p_begin, int64_t p_end, int zstride,
+                                            double *__restrict__ z, double *__restrict__ s,
+                                            double *__restrict__ ds_io,
+                                            int32_t *__restrict__ status,
+                                            int32_t *__restrict__ counters, const TrackDev &pr,
+                                            unsigned long long *queue,
+                                            unsigned long long *__restrict__ units) {
   const Geo<N> geo;
-  const int n = sd.n, r = geo.r;
+  const int r = geo.r;
   // per-group state in LDS: accepted point, Euler direction there, current dE and dN
   const int slot = (threadIdx.x >> 6) * Geo<N>::G + (geo.valid ? geo.g : 0);
-  Cx<double> *sZa = reinterpret_cast<Cx<double> *>(smem + table_bytes) + slot * 4 * N;
+  Cx<double> *sZa = slot_state + slot * 4 * N;
   Cx<double> *sEa = sZa + N;
   Cx<double> *sEc = sZa + 2 * N;
   Cx<double> *sNc = sZa + 3 * N;
+  const int64_t P = p_end - p_begin;
 
   double zr[N], zi[N];  // the path's point, replicated in every lane of the group
   double zo_r = 0.0, zo_i = 0.0;  // this lane's own coordinate z_r (same bits as zr[r], zi[r])
   double sc = 0.0, sa = 0.0, ds = 0.0, nrm_prev = 0.0;
   int64_t path = -1;
   int phase = PH_POLISH, k = 0, steps_here = 0, iters = 0;
-  bool has_acc = false;  // the slot's path has an accepted point (sZa, sEa, sa valid)
   bool need_exact = true;  // next evaluation recomputes the row maximum (fresh path, lost lag)
   double Mlag = 0.0;       // this lane's row maximum from the previous evaluation
+  bool force64 = false;    // mixed form: evaluate in FP64 until the next accepted point
+  int rej_run = 0;         // consecutive rejected steps since the last accepted point
+  bool stay64 = false;     // mixed form: this path evaluates in FP64 from now on
   int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   bool exhausted = !geo.valid;
 #pragma unroll
@@ -80,38 +91,34 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       if (need && r == 0) cl = atomicAdd(queue, 1ull);
       cl = __shfl(cl, geo.base, 64);
       if (need) {
-        // claims [0, P) take paths with a full or partial track ahead (fresh, resumed, handed
-        // over from the mixed form); claims [P, 2P) take the short pending endgames, so that the
-        // few long paths start first instead of forming the tail of the launch
-        const int64_t lim = MIXED ? P : 2 * P;
-        if ((int64_t)cl >= lim) {
+        if ((int64_t)cl >= P) {
           exhausted = true;
           need = false;
         } else {
-          const bool second = (int64_t)cl >= P;
-          const int64_t p = second ? (int64_t)cl - P : (int64_t)cl;
+          const int64_t p = p_begin + (int64_t)cl;
           const int st = status[p];
-          const bool fresh = !second && st == 1, pend = second && st == kPendingEnd;
-          const bool resume = !second && (st == 2 || (st == kHandoff && !MIXED));
-          if ((fresh || resume) || (pend && !MIXED)) {
+          const bool fresh = st == 1, resume = st == 2;
+          if (fresh || resume) {
             path = p;
             need = false;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-              zr[j] = j < n ? z[2 * (p * n + j)] : 0.0;
-              zi[j] = j < n ? z[2 * (p * n + j) + 1] : 0.0;
+              zr[j] = j < n ? z[2 * (p * zstride + j)] : 0.0;
+              zi[j] = j < n ? z[2 * (p * zstride + j) + 1] : 0.0;
             }
-            zo_r = r < n ? z[2 * (p * n + r)] : 0.0;
-            zo_i = r < n ? z[2 * (p * n + r) + 1] : 0.0;
+            zo_r = r < n ? z[2 * (p * zstride + r)] : 0.0;
+            zo_i = r < n ? z[2 * (p * zstride + r) + 1] : 0.0;
             sc = s[p];
             sa = sc;
             ds = fresh ? pr.ds0 : ds_io[p];
-            phase = fresh ? PH_POLISH : (resume ? PH_RESUME : PH_END);
+            phase = fresh ? PH_POLISH : PH_RESUME;
             k = 0;
             steps_here = 0;
             iters = 0;
             nrm_prev = 0.0;
-            has_acc = false;
+            force64 = false;
+            rej_run = 0;
+            stay64 = false;
             need_exact = true;  // also always true with pr.exact_shift
             c0 = counters[4 * p];
             c1 = counters[4 * p + 1];
@@ -125,28 +132,52 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
     const bool active = path >= 0;
 
     // ---- one evaluation + consolidated solve (every lane) ----
-    double nE, nN, resid, ratio;
-    Cx<double> e, q;
-    bool sing, shift_ok;
+    // Mixed form: a group evaluates in FP64 while it polishes its start point and in the
+    // endgame, after an FP32 evaluation failed (until the next accepted point), and for the rest
+    // of the path after kMixedFp64Rejects consecutive rejected steps; otherwise in FP32.  A wave
+    // runs each block only if one of its groups needs it.
+    bool use64 = true;
+    if constexpr (MIXED)
+      use64 = active && (phase == PH_END || phase == PH_POLISH || force64 || stay64);
+    double nE = 0.0, nN = 0.0, resid = 0.0, ratio = 0.0;
+    Cx<double> e = {0.0, 0.0}, q = {0.0, 0.0};
+    bool sing = false, shift_ok = true;
     {
+      const double Min = Mlag;
       double M;
       if constexpr (MIXED) {
-        Cx<float> row[N + 2], ef, qf;
-        float absum, rf;
-        shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Mlag, need_exact);
-        const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
-        sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
-        resid = group_max<N, double>((double)h2, r, geo.base);  // squared
-        e = {ef.x, ef.y};
-        q = {qf.x, qf.y};
-        ratio = rf;
-      } else {
-        Cx<double> row[N + 2];
-        double absum;
-        shift_ok = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Mlag, need_exact);
+        if (__any(!use64)) {
+          Cx<float> row[N + 2], ef, qf;
+          float absum, rf;
+          double Ml = Min;
+          shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
+          const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
+          sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
+          resid = group_max<N, double>((double)h2, r, geo.base);
+          e = {ef.x, ef.y};
+          q = {qf.x, qf.y};
+          ratio = rf;
+          Mlag = Ml;
+        }
+      }
+      if (__any(use64)) {
+        Cx<double> row[N + 2], ed, qd;
+        double absum, rd, nEd, nNd, Ml = Min;
+        const bool okd = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
         const double h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
-        sing = lu_solve2<N, double>(row, r, geo.base, n, e, q, nE, nN, ratio);
-        resid = group_max<N, double>(h2, r, geo.base);  // squared relative residual
+        const bool sd = lu_solve2<N, double>(row, r, geo.base, n, ed, qd, nEd, nNd, rd);
+        const double resd = group_max<N, double>(h2, r, geo.base);  // squared relative residual
+        if (use64) {
+          e = ed;
+          q = qd;
+          sing = sd;
+          ratio = rd;
+          nE = nEd;
+          nN = nNd;
+          resid = resd;
+          shift_ok = okd;
+          Mlag = Ml;
+        }
       }
     }
     // every lane of the group must have kept its terms in range, else redo with exact shifts
@@ -174,12 +205,14 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       const double nrm = nN;
       // the mixed form cannot resolve pivots below FP32's precision, nor polish below its
       // tracking tolerance: such points are rejected, or the path fails and is re-tracked in FP64
-      const double sing_ratio = MIXED ? fmax(pr.sing_ratio, 1e-7) : pr.sing_ratio;
-      const double tol_polish = MIXED ? fmax(pr.tol_polish, pr.tol_track) : pr.tol_polish;
+      const double sing_ratio = use64 ? pr.sing_ratio : fmax(pr.sing_ratio, 1e-7);
+      const double tol_polish = use64 ? pr.tol_polish : fmax(pr.tol_polish, pr.tol_track);
       const bool bad_lu = sing || !(ratio >= sing_ratio);
       const bool nonfin = !(nN <= INFINITY) || !(nE <= INFINITY);
       int act = ACT_NONE;
-      if (bad_lu || nonfin) {
+      if (MIXED && !use64 && (bad_lu || nonfin)) {
+        force64 = true;  // same point again, in FP64 (no state change)
+      } else if (bad_lu || nonfin) {
         if (phase == PH_TRACK) {
           act = ACT_REJECT;
         } else {
@@ -213,7 +246,8 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
         sZa[r] = Cx<double>{zo_r, zo_i};
         sEa[r] = e;
         sa = sc;
-        has_acc = true;
+        force64 = false;
+        rej_run = 0;
         if (sa >= 0.0) {
           phase = PH_END;
           k = 0;
@@ -252,6 +286,7 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       if (act == ACT_REJECT) {
         ++c1;
         ds *= 0.5;
+        if (MIXED && ++rej_run >= kMixedFp64Rejects) stay64 = true;
         if (ds < pr.ds_min) {
           fin = true;
           fst = -2;
@@ -292,10 +327,7 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
         phase = PH_TRACK;
       }
       if (act == ACT_END) {
-        if (MIXED) {
-          fin = true;
-          fst = kPendingEnd;  // FP64 endgame runs in the following launch
-        } else {
+        {
           double zn2 = 0.0;
 #pragma unroll
           for (int j = 0; j < N; ++j)
@@ -319,20 +351,11 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
         }
       }
     }
-    if (MIXED && fin && fst < 0 && fst != -7 && has_acc) {
-      // hand the path to the FP64 pass at its last accepted point
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      zo_r = sZa[r < N ? r : 0].x;
-      zo_i = sZa[r < N ? r : 0].y;
-      sc = sa;
-      ds = pr.ds0;
-      fst = kHandoff;
-    }
     if (fin) {
       const int64_t p = path;
       if (r < n) {
-        z[2 * (p * n + r)] = zo_r;
-        z[2 * (p * n + r) + 1] = zo_i;
+        z[2 * (p * zstride + r)] = zo_r;
+        z[2 * (p * zstride + r) + 1] = zo_i;
       }
       if (r == 0) {
         s[p] = sc;
@@ -347,6 +370,20 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
       path = -1;
     }
   }
+}
+
+// Single system: all P paths, one global work queue.  At most 256 registers per lane, so two
+// waves share each SIMD (the FP64 form at n = 10 needs slightly more without the bound).
+template <int N, bool MIXED>
+__global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_eu(2)))
+    k_track(SysDev sd, const double *__restrict__ c, int64_t P, double *__restrict__ z,
+            double *__restrict__ s, double *__restrict__ ds_io, int32_t *__restrict__ status,
+            int32_t *__restrict__ counters, TrackDev pr, unsigned long long *__restrict__ queue,
+            size_t table_bytes, unsigned long long *__restrict__ units) {
+  extern __shared__ __align__(16) char smem[];
+  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n, z,
+                        s, ds_io, status, counters, pr, queue, units);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
@@ -400,6 +437,182 @@ hipError_t launch_track(const System &S, const double *c, int64_t P, double *z, 
                         bool mixed, unsigned long long *queue, hipStream_t stream) {
   HOM_SWITCH_T(S.N, return track_n<NN>(S, c, P, z, s, ds, status, counters, pr, mixed, queue,
                                        stream))
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched form: many systems of uneven n and support sizes in one persistent launch.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kBatchStateBytes = 16 * 1024;  // >= 4 waves x G groups x 4N complex, any N
+
+// One work item: paths [p_begin, p_end) of system b, tracked by the block's lane groups sized
+// for b.N.  The tables go to LDS when they fit the budget, else they are read where they are.
+template <int N, bool MIXED>
+__device__ __forceinline__ void batch_item(char *smem, const BatchSysDev &b,
+                                           const double *__restrict__ T_all,
+                                           const int32_t *__restrict__ ints_all,
+                                           const double *__restrict__ c,
+                                           const Cx<double> *__restrict__ Cg,
+                                           const double *__restrict__ Cabs_g, int64_t p_begin,
+                                           int64_t p_end, int zstride, double *z, double *s,
+                                           double *ds, int32_t *status, int32_t *counters,
+                                           const TrackDev &pr, unsigned long long *lq,
+                                           unsigned long long *units, size_t table_budget) {
+  const SysDev sd{b.n, b.mmax, b.M, T_all + b.T_off, ints_all + b.ints_off,
+                  ints_all + b.ints_off + b.n};
+  SysLds<N> S;
+  if (b.lds_bytes > 0)
+    S = stage_tables<N>(smem, sd, c + 2 * b.c_off);  // block-uniform branch (one item per block)
+  else
+    S = SysLds<N>{sd.T, Cg + b.C_off, Cabs_g + b.C_off, sd.mk, b.n, b.mmax};
+  track_slots<N, MIXED>(S, b.n, reinterpret_cast<Cx<double> *>(smem + table_budget), p_begin,
+                        p_end, zstride, z, s, ds, status, counters, pr, lq, units);
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_eu(2)))
+    k_track_batch(const BatchSysDev *__restrict__ sys, int num_sys,
+                  const double *__restrict__ T_all, const int32_t *__restrict__ ints_all,
+                  const double *__restrict__ c, const Cx<double> *__restrict__ Cg,
+                  const double *__restrict__ Cabs_g, const int64_t *__restrict__ sys_off,
+                  const int64_t *__restrict__ item_off, int tile, int zstride,
+                  double *__restrict__ z, double *__restrict__ s, double *__restrict__ ds,
+                  int32_t *__restrict__ status, int32_t *__restrict__ counters, TrackDev pr,
+                  unsigned long long *__restrict__ gqueue, size_t table_budget,
+                  unsigned long long *__restrict__ units) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ unsigned long long lq;
+  __shared__ long long sh_item;
+  const int64_t n_items = item_off[num_sys];
+  for (;;) {
+    __syncthreads();  // the previous item is finished by every wave before LDS is reused
+    if (threadIdx.x == 0) {
+      sh_item = (long long)atomicAdd(gqueue, 1ull);
+      lq = 0ull;
+    }
+    __syncthreads();
+    const int64_t item = sh_item;
+    if (item >= n_items) break;
+    int lo = 0, hi = num_sys - 1;  // last system whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (item_off[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchSysDev b = sys[lo];
+    const int64_t first = item - item_off[lo];
+#define HOM_BATCH_CASE(NN)                                                                      \
+  case NN: {                                                                                  \
+    const int64_t chunk = (int64_t)tile * (kTrackBlock / 64) * Geo<NN>::G;                     \
+    const int64_t pb = sys_off[lo] + first * chunk;                                           \
+    const int64_t pe = pb + chunk < sys_off[lo + 1] ? pb + chunk : sys_off[lo + 1];           \
+    batch_item<NN, MIXED>(smem, b, T_all, ints_all, c, Cg, Cabs_g, pb, pe, zstride, z, s, ds,  \
+                          status, counters, pr, &lq, units, table_budget);                     \
+    break;                                                                                    \
+  }
+    switch (b.N) {
+      HOM_BATCH_CASE(2)
+      HOM_BATCH_CASE(3)
+      HOM_BATCH_CASE(4)
+      HOM_BATCH_CASE(5)
+      HOM_BATCH_CASE(6)
+      HOM_BATCH_CASE(7)
+      HOM_BATCH_CASE(8)
+      HOM_BATCH_CASE(10)
+      HOM_BATCH_CASE(12)
+      HOM_BATCH_CASE(16)
+      HOM_BATCH_CASE(20)
+      HOM_BATCH_CASE(24)
+      HOM_BATCH_CASE(32)
+      default:
+        break;
+    }
+#undef HOM_BATCH_CASE
+  }
+}
+
+// Per call: table-order coefficients and |c| of every system (used by systems read from global
+// memory), and each system's first path (sys_idx is non-decreasing).
+__global__ void k_batch_prep(const BatchSysDev *__restrict__ sys, int num_sys,
+                             const int32_t *__restrict__ ints_all, const double *__restrict__ c,
+                             const int32_t *__restrict__ sys_idx, int64_t P,
+                             Cx<double> *__restrict__ Cg, double *__restrict__ Cabs_g,
+                             int64_t *__restrict__ sys_off) {
+  const int sidx = blockIdx.x;
+  if (sidx < num_sys) {
+    const BatchSysDev b = sys[sidx];
+    const int32_t *mk = ints_all + b.ints_off, *off = mk + b.n;
+    for (int idx = threadIdx.x; idx < b.mmax * b.n; idx += blockDim.x) {
+      const int i = idx / b.n, r = idx - (idx / b.n) * b.n;
+      Cx<double> v = {0.0, 0.0};
+      if (i < mk[r]) {
+        const int64_t q = b.c_off + off[r] + i;
+        v.x = c[2 * q];
+        v.y = c[2 * q + 1];
+      }
+      Cg[b.C_off + idx] = v;
+      Cabs_g[b.C_off + idx] = sqrt(v.x * v.x + v.y * v.y);
+    }
+  }
+  if (threadIdx.x == 0 && sidx <= num_sys) {  // lower_bound(sys_idx, sidx)
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (sys_idx[mid] < sidx) lo = mid + 1;
+      else hi = mid;
+    }
+    sys_off[sidx] = lo;
+  }
+}
+
+// item_off[s] = number of work items before system s (one thread; num_sys is small).
+__global__ void k_batch_items(const BatchSysDev *__restrict__ sys, int num_sys, int tile,
+                              const int64_t *__restrict__ sys_off, int64_t *__restrict__ item_off) {
+  int64_t acc = 0;
+  for (int s = 0; s < num_sys; ++s) {
+    item_off[s] = acc;
+    const int N = sys[s].N;
+    const int64_t chunk = (int64_t)tile * (kTrackBlock / 64) * (64 / N);
+    const int64_t np = sys_off[s + 1] - sys_off[s];
+    acc += (np + chunk - 1) / chunk;
+  }
+  item_off[num_sys] = acc;
+}
+
+size_t track_batch_ws_bytes(const System &S) {
+  return 256 + (size_t)(S.num_sys + 1) * 16 + (size_t)S.C_total * 24 + 256;
+}
+
+hipError_t launch_track_batch(const System &S, const double *c, int64_t P, double *z, double *s,
+                              double *ds, const int32_t *sys_idx, int32_t *status,
+                              int32_t *counters, const TrackDev &pr, bool mixed, void *ws,
+                              hipStream_t stream) {
+  char *w = static_cast<char *>(ws);
+  unsigned long long *queue = reinterpret_cast<unsigned long long *>(w);
+  int64_t *sys_off = reinterpret_cast<int64_t *>(w + 256);
+  int64_t *item_off = sys_off + (S.num_sys + 1);
+  Cx<double> *Cg = reinterpret_cast<Cx<double> *>(item_off + (S.num_sys + 1));
+  double *Cabs_g = reinterpret_cast<double *>(Cg + S.C_total);
+  const int tile = pr.tile > 0 ? pr.tile : 4;
+  hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)(S.num_sys + 1)), dim3(256), 0, stream, S.dBatch,
+                     S.num_sys, S.dInts_all, c, sys_idx, P, Cg, Cabs_g, sys_off);
+  hipLaunchKernelGGL(k_batch_items, dim3(1), dim3(1), 0, stream, S.dBatch, S.num_sys, tile,
+                     sys_off, item_off);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, queue);
+  const size_t budget = (S.batch_lds + 15) & ~(size_t)15;
+  const size_t lds = budget + kBatchStateBytes;
+  auto kern = mixed ? k_track_batch<true> : k_track_batch<false>;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTrackBlock, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const unsigned blocks = (unsigned)(per_cu * num_cus());
+  prof_begin(stream);
+  unsigned long long *units = prof_units(stream);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kTrackBlock), lds, stream, S.dBatch, S.num_sys,
+                     S.dT_all, S.dInts_all, c, Cg, Cabs_g, sys_off, item_off, tile, S.n, z, s, ds,
+                     status, counters, pr, queue, budget, units);
+  prof_end(stream, mixed ? "k_track_batch<mixed>" : "k_track_batch<fp64>");
+  return hipGetLastError();
 }
 
 }  // namespace hom

@@ -245,6 +245,17 @@ def smith_normal_form(D):
 # --------------------------------------------------------------------------------------------
 # binomial start systems
 # --------------------------------------------------------------------------------------------
+def _randbelow(rng, bound):
+    """Seeded integer in [0, bound) for Python-int bounds of any size."""
+    if bound <= 2 ** 62:
+        return int(rng.integers(0, bound))
+    v, span = 0, 1
+    while span < bound * 2 ** 32:
+        v = v * 2 ** 62 + int(rng.integers(0, 2 ** 62))
+        span *= 2 ** 62
+    return v % bound
+
+
 def binomial_roots(Dmat, beta, count, rng):
     """`count` distinct roots of x^{d_k} = beta_k (rows d_k of Dmat), as z = log x.
 
@@ -271,7 +282,7 @@ def binomial_roots(Dmat, beta, count, rng):
     else:
         seen, ks = set(), []
         while len(ks) < count:
-            k = tuple(int(rng.integers(0, sg)) if sg > 1 else 0 for sg in sigma)
+            k = tuple(_randbelow(rng, sg) if sg > 1 else 0 for sg in sigma)
             if k not in seen:
                 seen.add(k)
                 ks.append(k)
@@ -281,11 +292,17 @@ def binomial_roots(Dmat, beta, count, rng):
     b = np.log(np.asarray(beta, np.complex128))
     z_base = np.linalg.solve(np.asarray(Dmat, np.float64), b)
     L = sigma[-1]
-    mult = [L // sg for sg in sigma]
+    # only coordinates with sigma_l > 1 take nonzero k_l; fold V's columns for them mod L once
+    live = [l for l in range(n) if sigma[l] > 1]
+    cols = {l: [(V[i][l] * (L // sigma[l])) % L for i in range(n)] for l in live}
     z = np.empty((len(ks), n), dtype=np.complex128)
     for q, k in enumerate(ks):
-        frac = [(sum(V[i][l] * k[l] * mult[l] for l in range(n)) % L) / L for i in range(n)]
-        z[q] = z_base + 2j * np.pi * np.array(frac)
+        num = [0] * n
+        for l in live:
+            if k[l]:
+                col = cols[l]
+                num = [a + k[l] * b for a, b in zip(num, col)]
+        z[q] = z_base + 2j * np.pi * np.array([(v % L) / L for v in num])
     z = z.real + 1j * (np.mod(z.imag + np.pi, 2.0 * np.pi) - np.pi)
     return np.ascontiguousarray(z)
 
