@@ -100,6 +100,80 @@ def run_form(hom, torch, h, csys, z0, precision, steps, warmup):
                 launches={k: len(v) for k, v in kern.items()}, paths_per_s=P * steps / sec)
 
 
+# dense-support configuration: n = 32, 128 monomials per equation, 262144 points (eval and step)
+C3_N, C3_M = 32, 128
+C3_MONO = C3_N * C3_M
+#   A1 2 (2n + 1) M = 532480, A2 8 M = 32768, A3 M (4n + 6) = 548864  (FMA = 2 flops)
+C3_FLOPS_EVAL = 2 * (2 * C3_N + 1) * C3_MONO + 8 * C3_MONO + C3_MONO * (4 * C3_N + 6)
+#   A5 on the 32 x 32 complex J with 2 right-hand sides: (8/3) n^3 + 16 n^2
+C3_FLOPS_LU = int(8 * C3_N ** 3 / 3 + 16 * C3_N ** 2)
+# matrix-core work the engines issue per point (the BF16x3 split repeats products)
+#   BF16x3: per 16 monomials x 16 points, 1 + 6 MFMA 16x16x32 for A1 (row maximum, then hi/mid/lo
+#           of Re and of the three phase digits); per 32 monomials x 16 points 6 MFMA per
+#           16-column tile for A3 (Re/Im x hi/mid/lo), two column tiles
+C3_MFMA_BF16 = C3_MONO * ((1 + 6) * 16384 / 256 + 6 * 2 * 16384 / 512)
+#   FP64: per 16 x 16, 8 + 8 MFMA 16x16x4 f64 (Re, Im; K = 32 in steps of 4) for A1, 4 x 2 x 2 for
+#         A3 (K = 4 monomials at a time, two column tiles, Re/Im)
+C3_MFMA_F64 = C3_MONO * ((8 + 8) * 2048 / 256 + 16 * 2048 / 256)
+PEAK_BF16 = 2.5e15
+
+
+def run_dense(hom, torch, P, reps=3):
+    """Dense-support eval and step at n = 32, m = 128: per engine, kernel ms (library events),
+    points/s, algorithmic TFLOP/s and the matrix-core issue rate."""
+    import workloads as W
+    sys_, z, s = W.config_system("c3", P=P)
+    dev = "cuda"
+    c = torch.tensor(sys_.c, dtype=torch.complex128, device=dev)
+    zt = torch.tensor(z, dtype=torch.complex128, device=dev)
+    st = torch.tensor(s, dtype=torch.float64, device=dev)
+    h = hom.System.from_workload(sys_)
+    out = {}
+    legs = [("eval_mfma_fp64", "eval", 0), ("eval_mfma_bf16x3", "eval", hom.EVAL_FP32),
+            ("eval_valu_fp64", "eval", hom.EVAL_VALU), ("step_mfma_fp64", "step", hom.FP64),
+            ("step_mfma_bf16x3", "step", hom.MIXED)]
+    for name, kind, arg in legs:
+        def once():
+            if kind == "eval":
+                G, L = hom.eval(h, c, zt, st, flags=arg)
+                del G, L
+            else:
+                r = hom.step(h, c, zt, st, precision=arg)
+                del r
+        once()
+        torch.cuda.synchronize()
+        hom.profile_read()
+        hom.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        hom.set_profiling(False)
+        kern = {}
+        for kname, ms, _u in hom.profile_read():
+            kern[kname] = kern.get(kname, 0.0) + ms / reps
+        ms = sum(kern.values())
+        flops = C3_FLOPS_EVAL + (C3_FLOPS_LU if kind == "step" else 0)
+        rec = {"kernels_ms": kern, "ms": ms, "wall_ms": wall * 1e3, "points_per_s": P / (ms * 1e-3),
+               "tflops_algorithmic": P * flops / (ms * 1e-3) / 1e12}
+        ek = [k for k in kern if k.startswith("k_dense<") or k.startswith("k_eval<")]
+        if ek:
+            ems = sum(kern[k] for k in ek)
+            rec["eval_kernel_ms"] = ems
+            if "bf16x3" in name:
+                rec["mfma_tflops_issued"] = P * C3_MFMA_BF16 / (ems * 1e-3) / 1e12
+                rec["mfma_frac_of_bf16_peak"] = P * C3_MFMA_BF16 / (ems * 1e-3) / PEAK_BF16
+            elif "mfma_fp64" in name:
+                rec["mfma_tflops_issued"] = P * C3_MFMA_F64 / (ems * 1e-3) / 1e12
+                rec["mfma_frac_of_fp64_peak"] = P * C3_MFMA_F64 / (ems * 1e-3) / PEAK_FP64
+            rec["frac_of_fp64_peak_algorithmic"] = P * C3_FLOPS_EVAL / (ems * 1e-3) / PEAK_FP64
+        out[name] = rec
+        print(f"# c3 {name}: {ms:.2f} ms, {rec['points_per_s']:.3e} points/s, kernels {kern}",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(csys, z0, target_s=15.0):
     """The oracle (unchanged) tracking a bounded sample of the same paths on the host cores."""
     import numpy as np
@@ -127,6 +201,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--paths", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense-support (n=32, m=128) eval/step leg")
+    ap.add_argument("--dense-points", type=int, default=262144)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 512 MiB device-to-device copy (scales HBM counters)")
     args = ap.parse_args()
@@ -187,6 +264,8 @@ def main():
                   "kernel_units": mixed["units"]},
         "roofline": roof,
     }
+    if not args.no_dense:
+        out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(csys, z0)
     print(json.dumps(out), flush=True)

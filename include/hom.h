@@ -52,7 +52,13 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
 #define HOM_UNSCALED 1 /* multiply row k back by e^{logscale_k} (may overflow) */
 #define HOM_AFFINE 2   /* return J_x = J_z diag(e^{-z}) and H_t = e^{-s} H_s instead */
 #define HOM_EVAL_FP32 4 /* the mixed form's evaluation: FP32 exponentials and contraction
-                           (exponent sums still FP64), results widened to FP64 */
+                           (exponent sums still FP64), results widened to FP64; on a handle
+                           with matrix-core tables: the BF16x3 engine (below) */
+#define HOM_EVAL_VALU 8 /* on a handle with matrix-core tables, use the vector-unit kernels
+                           (one lane per equation) instead */
+
+/* hom_create flags */
+#define HOM_CREATE_VALU 1 /* build no matrix-core tables (see hom_create) */
 
 /* per-path status (hom_step: OK or SINGULAR; hom_track: all) */
 #define HOM_PATH_OK 0            /* reached s = 0, endgame converged, residual <= res_tol */
@@ -68,10 +74,17 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
 
 /*
  * Create a system handle (the initialisation step of Sec. 7, Alg. 1): validates the input,
- * copies A and w to the device and builds the per-equation tables the kernels stage into LDS.
- * n in [1, 32]; m[k] >= 1; M <= 65536.  Synchronous.  flags must be 0.
- * Errors: HOM_EINVAL (bad argument), HOM_ENOMEM, HOM_EDEVICE, HOM_EUNSUPPORTED (tables larger
- * than the kernels can stage).
+ * copies A and w to the device and builds the per-equation tables the kernels stage into LDS
+ * (tables beyond the 48 KB LDS budget are read from global memory instead, and each compute call
+ * then builds its coefficient table in a stream-ordered workspace).
+ * When the largest m_k is at least 32 (a dense support) it also builds the matrix-core tables:
+ * hom_eval and hom_step then run the two contractions of Sec. 5.1 on MFMA, per equation and per
+ * tile of 16 points (FP64: 16x16x4 f64 MFMA; HOM_EVAL_FP32 / HOM_MIXED: BF16x3, i.e. z and the
+ * exponentials split into three bf16 parts with FP32 accumulation, the phase formed exactly
+ * from integer digit sums); hom_step keeps the LU on the vector units.  flags: 0 or
+ * HOM_CREATE_VALU (no matrix-core tables).
+ * n in [1, 32]; m[k] >= 1; M <= 65536.  Synchronous.
+ * Errors: HOM_EINVAL (bad argument), HOM_ENOMEM, HOM_EDEVICE.
  */
 int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int flags,
                hom_system_t *out);
@@ -107,7 +120,8 @@ int hom_system_info(hom_system_t sys, int *n, int64_t *M, int *m_max, int *num_s
  * <a, Re z_p> + w(a) s_p over the monomials of equation k (so no term over- or underflows).
  * c: complex128 [M]; z: complex128 [P][n]; s: double [P]; G: complex128 [P][n][n+2];
  * logscale: double [P][n] or NULL (zeros with HOM_UNSCALED).  flags: any of HOM_UNSCALED,
- * HOM_AFFINE, HOM_EVAL_FP32.  P = 0 is a no-op.
+ * HOM_AFFINE, HOM_EVAL_FP32, HOM_EVAL_VALU.  On the matrix-core engines the shift logscale is
+ * the row maximum to within about 0.1 (any shift gives the same directions).  P = 0 is a no-op.
  */
 int hom_eval(hom_system_t sys, const double *c, int64_t P, const double *z, const double *s,
              double *G, double *logscale, int flags, hom_stream_t stream);

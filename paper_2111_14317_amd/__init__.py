@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libhom.so")
 
 HOM_OK, HOM_EINVAL, HOM_ENOMEM, HOM_EDEVICE, HOM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
-UNSCALED, AFFINE, EVAL_FP32 = 1, 2, 4
+UNSCALED, AFFINE, EVAL_FP32, EVAL_VALU = 1, 2, 4, 8
+CREATE_VALU = 1
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
@@ -109,25 +110,27 @@ def default_params(precision=FP64, **overrides) -> TrackParams:
 
 
 class System:
-    """A system handle (Alg. 1): exponents A int8 [M][n] equation-major, liftings w [M]."""
+    """A system handle (Alg. 1): exponents A int8 [M][n] equation-major, liftings w [M].
+    With the largest m_k >= 32 the handle also carries matrix-core tables (dense supports), and
+    eval / step run the MFMA engines unless `valu` is set (or eval gets EVAL_VALU)."""
 
     num_sys = 1
 
-    def __init__(self, n, m, A, w):
+    def __init__(self, n, m, A, w, valu=False):
         m = np.ascontiguousarray(m, np.int32)
         A = np.ascontiguousarray(A, np.int8)
         w = np.ascontiguousarray(w, np.float64)
         h = ctypes.c_void_p()
         _check(lib.hom_create(int(n), m.ctypes.data_as(ctypes.c_void_p),
                               A.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
-                              0, ctypes.byref(h)))
+                              CREATE_VALU if valu else 0, ctypes.byref(h)))
         self.handle = h
         self.n = int(n)
         self.M = int(m.sum())
 
     @classmethod
-    def from_workload(cls, sys):
-        return cls(sys.n, sys.m, sys.A, sys.w)
+    def from_workload(cls, sys, valu=False):
+        return cls(sys.n, sys.m, sys.A, sys.w, valu=valu)
 
     def close(self):
         if self.handle:

@@ -165,6 +165,65 @@ static void build_table(int n, int N, const int32_t *m, const int8_t *A, const d
     }
 }
 
+// Matrix-core tables of a dense-support system, laid out for the 16x16 MFMA operand lanes
+// (lane l: row / column l % 16, K block l / 16).  Each equation's monomials are padded to a
+// multiple of 32 with copies of its first monomial (the padding gets coefficient 0 per call).
+struct DenseHost {
+  int Md = 0;
+  std::vector<int32_t> tile0, src;
+  std::vector<uint16_t> EAb, CBb;  // bf16 bit patterns (small integers: exact)
+  std::vector<double> EAd, CBd, W;
+};
+
+static uint16_t bf16_of_int(int v) {
+  const float f = (float)v;  // |v| <= 127: exact in 8 significant bits
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+
+static void build_dense(int n, const int32_t *m, const int8_t *A, const double *w,
+                        const std::vector<int32_t> &off, DenseHost &D) {
+  std::vector<int32_t> doff(n + 1, 0);
+  for (int k = 0; k < n; ++k) doff[k + 1] = doff[k] + (m[k] + 31) / 32 * 32;
+  const int Md = doff[n];
+  D.Md = Md;
+  D.tile0.resize(n + 1);
+  for (int k = 0; k <= n; ++k) D.tile0[k] = doff[k] / 16;
+  D.src.assign(Md, -1);
+  std::vector<int32_t> mono(Md);  // monomial whose exponents and lifting slot d carries
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < doff[k + 1] - doff[k]; ++i) {
+      mono[doff[k] + i] = off[k] + (i < m[k] ? i : 0);
+      if (i < m[k]) D.src[doff[k] + i] = off[k] + i;
+    }
+  auto a = [&](int d, int j) -> int { return j < n ? (int)A[(size_t)mono[d] * n + j] : 0; };
+  const int ntile = Md / 16;
+  D.EAb.assign((size_t)ntile * 64 * 8, 0);
+  D.EAd.assign((size_t)ntile * 8 * 64, 0.0);
+  D.CBd.assign((size_t)ntile * 4 * 2 * 64, 0.0);
+  D.CBb.assign((size_t)(Md / 32) * 2 * 64 * 8, 0);
+  D.W.resize(Md);
+  for (int d = 0; d < Md; ++d) D.W[d] = w[mono[d]];
+  for (int t = 0; t < ntile; ++t)
+    for (int l = 0; l < 64; ++l) {
+      for (int e = 0; e < 8; ++e)  // A1 bf16 A operand: row = monomial, K = coordinate
+        D.EAb[((size_t)t * 64 + l) * 8 + e] = bf16_of_int(a(16 * t + l % 16, 8 * (l / 16) + e));
+      for (int ks = 0; ks < 8; ++ks)  // A1 FP64 A operand
+        D.EAd[((size_t)t * 8 + ks) * 64 + l] = a(16 * t + l % 16, 4 * ks + l / 16);
+      for (int r = 0; r < 4; ++r)  // A3 FP64 B operand: K = monomial 4(l/16) + r of the tile
+        for (int ct = 0; ct < 2; ++ct)
+          D.CBd[(((size_t)t * 4 + r) * 2 + ct) * 64 + l] =
+              a(16 * t + 4 * (l / 16) + r, 16 * ct + l % 16);
+    }
+  for (int ch = 0; ch < Md / 32; ++ch)  // A3 bf16 B operand: element e of K block l/16 is
+    for (int ct = 0; ct < 2; ++ct)      // monomial 32 ch + 16 (e / 4) + 4 (l / 16) + e % 4
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e)
+          D.CBb[(((size_t)ch * 2 + ct) * 64 + l) * 8 + e] =
+              bf16_of_int(a(32 * ch + 16 * (e / 4) + 4 * (l / 16) + e % 4, 16 * ct + l % 16));
+}
+
 static void free_system(System &S) {
   hipFree(S.dT);
   hipFree(S.dmk);
@@ -173,6 +232,24 @@ static void free_system(System &S) {
   hipFree(S.dBatch);
   hipFree(S.dT_all);
   hipFree(S.dInts_all);
+  hipFree(S.dDense);
+}
+
+// This call's table-order coefficients for a system whose tables stay in global memory (a
+// stream-ordered workspace, freed by coeff_end); nothing for systems staged in LDS.
+static hipError_t coeff_begin(const System &S, const double *c, hipStream_t st, void **cws) {
+  *cws = nullptr;
+  if (!S.global_tables) return hipSuccess;
+  hipError_t e = hipMallocAsync(cws, S.coeff_ws_bytes(), st);
+  if (e != hipSuccess) {
+    *cws = nullptr;
+    return e;
+  }
+  return launch_coeff_tables(S, c, *cws, st);
+}
+
+static hipError_t coeff_end(void *cws, hipStream_t st) {
+  return cws ? hipFreeAsync(cws, st) : hipSuccess;
 }
 
 extern "C" {
@@ -223,16 +300,13 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   g_err.clear();
   if (!out) HOM_FAIL(HOM_EINVAL, "hom_create: out is NULL");
   *out = nullptr;
-  if (flags != 0) HOM_FAIL(HOM_EINVAL, "hom_create: flags must be 0");
+  if (flags & ~HOM_CREATE_VALU) HOM_FAIL(HOM_EINVAL, "hom_create: unknown flags");
   int64_t M = 0;
   int mmax = 0;
   const std::string bad = validate_system(n, m, A, w, &M, &mmax);
   if (!bad.empty()) HOM_FAIL(HOM_EINVAL, "hom_create: " + bad);
   const int N = bucket_for(n);
   const size_t lds = lds_for(N, n, mmax);
-  if (lds > kMaxLds)
-    HOM_FAIL(HOM_EUNSUPPORTED, "hom_create: system tables exceed the LDS budget (" +
-                                   std::to_string(lds) + " bytes); use hom_create_batch");
   std::vector<double> T;
   std::vector<int32_t> off;
   build_table(n, N, m, A, w, mmax, T, off);
@@ -245,7 +319,9 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   S.N = N;
   S.mmax = mmax;
   S.M = (int)M;
-  S.lds_bytes = lds;
+  // tables beyond the LDS budget stay in global memory (read through the caches)
+  S.global_tables = lds > kMaxLds;
+  S.lds_bytes = S.global_tables ? 0 : lds;
   auto fail = [&](hipError_t e, const char *what) {
     set_error(std::string("hom_create: ") + what + ": " + hipGetErrorString(e));
     free_system(S);
@@ -266,6 +342,39 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
     return fail(e, "hipMemcpy");
   if ((e = hipMemcpy(S.dA, A32.data(), A32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "hipMemcpy");
+  if (mmax >= kDenseMinM && !(flags & HOM_CREATE_VALU)) {
+    DenseHost D;
+    build_dense(n, m, A, w, off, D);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_tile0 = 0, o_src = o_tile0 + al(D.tile0.size() * 4);
+    const size_t o_EAb = o_src + al(D.src.size() * 4), o_EAd = o_EAb + al(D.EAb.size() * 2);
+    const size_t o_CBb = o_EAd + al(D.EAd.size() * 8), o_CBd = o_CBb + al(D.CBb.size() * 2);
+    const size_t o_W = o_CBd + al(D.CBd.size() * 8), total = o_W + al(D.W.size() * 8);
+    std::vector<char> img(total, 0);
+    memcpy(img.data() + o_tile0, D.tile0.data(), D.tile0.size() * 4);
+    memcpy(img.data() + o_src, D.src.data(), D.src.size() * 4);
+    memcpy(img.data() + o_EAb, D.EAb.data(), D.EAb.size() * 2);
+    memcpy(img.data() + o_EAd, D.EAd.data(), D.EAd.size() * 8);
+    memcpy(img.data() + o_CBb, D.CBb.data(), D.CBb.size() * 2);
+    memcpy(img.data() + o_CBd, D.CBd.data(), D.CBd.size() * 8);
+    memcpy(img.data() + o_W, D.W.data(), D.W.size() * 8);
+    if ((e = hipMalloc(&S.dDense, total)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipMemcpy(S.dDense, img.data(), total, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "hipMemcpy");
+    char *b = static_cast<char *>(S.dDense);
+    S.Md = D.Md;
+    S.dense = DenseDev{n,
+                       (n + 15) / 16,
+                       (n + 3) / 4,
+                       D.Md,
+                       reinterpret_cast<const int32_t *>(b + o_tile0),
+                       reinterpret_cast<const int32_t *>(b + o_src),
+                       reinterpret_cast<const uint4 *>(b + o_EAb),
+                       reinterpret_cast<const double *>(b + o_EAd),
+                       reinterpret_cast<const uint4 *>(b + o_CBb),
+                       reinterpret_cast<const double *>(b + o_CBd),
+                       reinterpret_cast<const double *>(b + o_W)};
+  }
   *out = h;
   return HOM_OK;
 }
@@ -375,10 +484,27 @@ int hom_eval(hom_system_t h, const double *c, int64_t P, const double *z, const 
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL handle");
   if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_eval: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_eval: P < 0");
-  if (flags & ~7) HOM_FAIL(HOM_EINVAL, "hom_eval: unknown flags");
+  if (flags & ~15) HOM_FAIL(HOM_EINVAL, "hom_eval: unknown flags");
   if (P == 0) return HOM_OK;
   if (!c || !z || !s || !G) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL array");
-  HOM_HIP(launch_eval(h->s, c, P, z, s, G, logscale, flags, (hipStream_t)stream), "hom_eval");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->s.has_dense() && !(flags & HOM_EVAL_VALU)) {  // matrix-core engines
+    const int engine = (flags & HOM_EVAL_FP32) ? 1 : 0;
+    void *dws = nullptr;
+    HOM_HIP(hipMallocAsync(&dws, dense_ws_bytes(h->s, P, false, engine), st),
+            "hom_eval: workspace");
+    hipError_t e = launch_dense_eval(h->s, c, P, z, s, G, logscale, flags & 3, engine, dws, st);
+    hipError_t e2 = hipFreeAsync(dws, st);
+    HOM_HIP(e, "hom_eval");
+    HOM_HIP(e2, "hom_eval: free workspace");
+    return HOM_OK;
+  }
+  void *cws = nullptr;
+  hipError_t e = coeff_begin(h->s, c, st, &cws);
+  if (e == hipSuccess) e = launch_eval(h->s, cws, c, P, z, s, G, logscale, flags & 7, st);
+  hipError_t e2 = coeff_end(cws, st);
+  HOM_HIP(e, "hom_eval");
+  HOM_HIP(e2, "hom_eval: free workspace");
   return HOM_OK;
 }
 
@@ -394,9 +520,23 @@ int hom_step(hom_system_t h, const double *c, int64_t P, const double *z, const 
   if (P == 0) return HOM_OK;
   if (!c || !z || !s || !dz_euler || !dz_newton || !status)
     HOM_FAIL(HOM_EINVAL, "hom_step: NULL array");
-  HOM_HIP(launch_step(h->s, c, P, z, s, dz_euler, dz_newton, status, precision,
-                      (hipStream_t)stream),
-          "hom_step");
+  hipStream_t st = (hipStream_t)stream;
+  void *cws = nullptr, *dws = nullptr;
+  hipError_t e = coeff_begin(h->s, c, st, &cws);
+  if (h->s.has_dense()) {  // matrix-core evaluation, then the LU on the stored rows
+    if (e == hipSuccess)
+      e = hipMallocAsync(&dws, dense_ws_bytes(h->s, P, true, precision == HOM_MIXED ? 1 : 0), st);
+    if (e == hipSuccess)
+      e = launch_dense_step(h->s, cws, c, P, z, s, dz_euler, dz_newton, status, precision, dws,
+                            st);
+  } else if (e == hipSuccess) {
+    e = launch_step(h->s, cws, c, P, z, s, dz_euler, dz_newton, status, precision, st);
+  }
+  hipError_t e2 = coeff_end(cws, st);
+  hipError_t e3 = dws ? hipFreeAsync(dws, st) : hipSuccess;
+  HOM_HIP(e, "hom_step");
+  HOM_HIP(e2, "hom_step: free workspace");
+  HOM_HIP(e3, "hom_step: free workspace");
   return HOM_OK;
 }
 
@@ -466,14 +606,19 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     HOM_HIP(e2, "hom_track: free workspace");
     return HOM_OK;
   }
-  // workspace: the device work-queue counter
+  // workspace: the device work-queue counter (+ the coefficient tables of a global-table system)
   unsigned long long *queue = nullptr;
   HOM_HIP(hipMallocAsync((void **)&queue, 256, st), "hom_track: workspace");
-  e = launch_track(h->s, c, P, z, s, ds, status, counters, pr, params->precision == HOM_MIXED,
-                   queue, st);
-  hipError_t e2 = hipFreeAsync(queue, st);
-  if (e != hipSuccess) HOM_HIP(e, "hom_track");
+  void *cws = nullptr;
+  e = coeff_begin(h->s, c, st, &cws);
+  if (e == hipSuccess)
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr,
+                     params->precision == HOM_MIXED, queue, st);
+  hipError_t e2 = coeff_end(cws, st);
+  hipError_t e3 = hipFreeAsync(queue, st);
+  HOM_HIP(e, "hom_track");
   HOM_HIP(e2, "hom_track: free workspace");
+  HOM_HIP(e3, "hom_track: free workspace");
   return HOM_OK;
 }
 
@@ -491,10 +636,15 @@ int hom_endpoint_grad(hom_system_t h, const double *c, int64_t P, const double *
   const size_t elems = grad_work_elems(h->s, P);
   double *work = nullptr;
   HOM_HIP(hipMallocAsync((void **)&work, elems * 8, st), "hom_endpoint_grad: workspace");
-  hipError_t e = launch_grad(h->s, c, P, z_end, grad_x, grad_c, precision, work, elems, st);
-  hipError_t e2 = hipFreeAsync(work, st);
-  if (e != hipSuccess) HOM_HIP(e, "hom_endpoint_grad");
+  void *cws = nullptr;
+  hipError_t e = coeff_begin(h->s, c, st, &cws);
+  if (e == hipSuccess)
+    e = launch_grad(h->s, cws, c, P, z_end, grad_x, grad_c, precision, work, elems, st);
+  hipError_t e2 = coeff_end(cws, st);
+  hipError_t e3 = hipFreeAsync(work, st);
+  HOM_HIP(e, "hom_endpoint_grad");
   HOM_HIP(e2, "hom_endpoint_grad: free workspace");
+  HOM_HIP(e3, "hom_endpoint_grad: free workspace");
   return HOM_OK;
 }
 

@@ -134,6 +134,11 @@ struct SysDev {
   const double *T;    // [mmax][n][LD] exponents (as doubles, zero padded to N) + lifting
   const int32_t *mk;  // [n]
   const int32_t *off; // [n] offset of equation k in the equation-major arrays
+  // Tables too large for LDS stay in global memory: then Cg / Cabs_g hold this call's
+  // coefficients and their moduli in table order [mmax][n] (built by a prologue kernel),
+  // otherwise both are null and the block stages everything into LDS.
+  const Cx<double> *Cg;
+  const double *Cabs_g;
 };
 
 // LDS image of a system: exponent table, coefficients in table order, |c|, m_k.
@@ -152,8 +157,10 @@ __host__ __device__ constexpr size_t lds_table_bytes(int n, int mmax) {
 }
 
 // Cooperative copy of the tables into LDS (whole block).  c: complex128 [M] equation-major.
+// For a system whose tables stay in global memory this only returns the global pointers.
 template <int N>
 __device__ SysLds<N> stage_tables(char *smem, const SysDev &sd, const double *__restrict__ c) {
+  if (sd.Cg) return SysLds<N>{sd.T, sd.Cg, sd.Cabs_g, sd.mk, sd.n, sd.mmax};
   constexpr int LD = TableLD<N>::value;
   const int n = sd.n, mmax = sd.mmax;
   double *sT = reinterpret_cast<double *>(smem);

@@ -26,6 +26,25 @@ struct BatchSysDev {
   int pad;
 };
 
+// Matrix-core tables of a dense-support system (built by hom_create when the largest m_k is at
+// least kDenseMinM).  Each equation's monomials are padded to a multiple of 32 with copies of its
+// first monomial (coefficient 0), so 16-monomial tiles and 32-monomial chunks never straddle two
+// equations.  Lane layouts are those of the gfx950 16x16 MFMA operands.
+constexpr int kDenseMinM = 32;
+struct DenseDev {
+  int n;                 // unknowns
+  int nct;               // 16-column tiles of the Jacobian (ceil(n / 16))
+  int nks;               // K steps of 4 coordinates for the FP64 engine (ceil(n / 4))
+  int Md;                // padded monomials
+  const int32_t *tile0;  // [n + 1] first 16-monomial tile of equation k (tile0[n] = Md / 16)
+  const int32_t *src;    // [Md] monomial index into c, or -1 for padding
+  const uint4 *EAb;      // [Md/16][64] bf16x8: exponents a[16t + l%16][8(l/16) + e] (A operand)
+  const double *EAd;     // [Md/16][8][64]: a[16t + l%16][4ks + l/16] (FP64 A operand)
+  const uint4 *CBb;      // [Md/32][2][64] bf16x8: exponent columns, bf16 engine B operand
+  const double *CBd;     // [Md/16][4][2][64]: exponent columns, FP64 engine B operand
+  const double *W;       // [Md] lifting
+};
+
 struct System {
   int n = 0, N = 0, mmax = 0, M = 0;
   // batched form (num_sys > 0): n = largest n, M = total, mmax = largest m_k
@@ -41,8 +60,20 @@ struct System {
   int32_t *dmk = nullptr;   // device [n]
   int32_t *doff = nullptr;  // device [n]
   int32_t *dA = nullptr;    // device [M][n] exponents as int32 (adjoint kernel)
-  size_t lds_bytes = 0;     // LDS image of the tables
-  SysDev dev() const { return SysDev{n, mmax, M, dT, dmk, doff}; }
+  size_t lds_bytes = 0;     // LDS image of the tables; 0 when they stay in global memory
+  bool global_tables = false;
+  // cws: this call's table-order coefficients (coeff_ws_bytes), for global_tables only
+  SysDev dev(const void *cws = nullptr) const {
+    const Cx<double> *Cg = global_tables ? static_cast<const Cx<double> *>(cws) : nullptr;
+    const double *Ca = Cg ? reinterpret_cast<const double *>(Cg + (size_t)mmax * n) : nullptr;
+    return SysDev{n, mmax, M, dT, dmk, doff, Cg, Ca};
+  }
+  size_t coeff_ws_bytes() const { return global_tables ? (size_t)mmax * n * 24 : 0; }
+  // matrix-core tables (dense supports); null pointers when not built
+  int Md = 0;
+  void *dDense = nullptr;  // one allocation holding every DenseDev array
+  DenseDev dense{};
+  bool has_dense() const { return dDense != nullptr; }
 };
 
 // Tracker constants as the kernels see them.
@@ -63,25 +94,39 @@ void prof_begin(hipStream_t stream);
 unsigned long long *prof_units(hipStream_t stream);
 void prof_end(hipStream_t stream, const char *label);
 
-// launchers (return a hipError_t)
-hipError_t launch_eval(const System &S, const double *c, int64_t P, const double *z,
-                       const double *s, double *G, double *logscale, int flags,
+// launchers (return a hipError_t).  cws: the per-call coefficient workspace of a system with
+// global tables (filled by launch_coeff_tables first), else null.
+hipError_t launch_coeff_tables(const System &S, const double *c, void *cws, hipStream_t stream);
+hipError_t launch_eval(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z, const double *s, double *G, double *logscale, int flags,
                        hipStream_t stream);
-hipError_t launch_step(const System &S, const double *c, int64_t P, const double *z,
-                       const double *s, double *dE, double *dN, int32_t *status, int precision,
-                       hipStream_t stream);
-hipError_t launch_track(const System &S, const double *c, int64_t P, double *z, double *s,
-                        double *ds, int32_t *status, int32_t *counters, const TrackDev &pr,
-                        bool mixed, unsigned long long *queue, hipStream_t stream);
+hipError_t launch_step(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z, const double *s, double *dE, double *dN,
+                       int32_t *status, int precision, hipStream_t stream);
+hipError_t launch_track(const System &S, const void *cws, const double *c, int64_t P, double *z,
+                        double *s, double *ds, int32_t *status, int32_t *counters,
+                        const TrackDev &pr, bool mixed, unsigned long long *queue,
+                        hipStream_t stream);
 hipError_t launch_track_batch(const System &S, const double *c, int64_t P, double *z, double *s,
                               double *ds, const int32_t *sys_idx, int32_t *status,
                               int32_t *counters, const TrackDev &pr, bool mixed, void *ws,
                               hipStream_t stream);
 size_t track_batch_ws_bytes(const System &S);
-hipError_t launch_grad(const System &S, const double *c, int64_t P, const double *z_end,
+hipError_t launch_grad(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z_end,
                        const double *grad_x, double *grad_c, int precision, double *work,
                        size_t work_elems, hipStream_t stream);
 size_t grad_work_elems(const System &S, int64_t P);
+
+// Dense-support evaluation and step on the matrix cores.  engine: 0 = FP64 MFMA, 1 = BF16x3 MFMA
+// with FP32 accumulation.  dws: dense_ws_bytes(S, P, step) bytes of workspace.
+size_t dense_ws_bytes(const System &S, int64_t P, bool step, int engine);
+hipError_t launch_dense_eval(const System &S, const double *c, int64_t P, const double *z,
+                             const double *s, double *G, double *logscale, int flags, int engine,
+                             void *dws, hipStream_t stream);
+hipError_t launch_dense_step(const System &S, const void *cws, const double *c, int64_t P,
+                             const double *z, const double *s, double *dE, double *dN,
+                             int32_t *status, int precision, void *dws, hipStream_t stream);
 
 // number of compute units of the current device (cached)
 int num_cus();

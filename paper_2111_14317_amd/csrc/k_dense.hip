@@ -1,0 +1,624 @@
+// Dense-support evaluation on the matrix cores (large m_k, e.g. n = 32 with 128 monomials per
+// equation).  Per equation k and per tile of 16 points:
+//
+//   A1  u = [A_k | w_k] [z; s]          MFMA, rows = monomials, columns = points (Sec. 5.1, the
+//                                       exponent product e^{Z A})
+//   A2  V = c exp(u - M_k)              vector units, in the MFMA result layout
+//   A3  [J_z | H_s | H]_k = V C_k       MFMA with V as the A operand straight from the A1 result
+//                                       registers (Sec. 5.1, the per-equation product with B_k);
+//                                       the w and 1 columns (H_s, H) are summed on the vector units
+//
+// Two engines:
+//   FP64    16x16x4 f64 MFMA; phase in turns (z's imaginary parts divided by 2 pi and reduced
+//           before the product), exp and sincospi in FP64.
+//   BF16x3  16x16x32 bf16 MFMA with FP32 accumulation.  Re z is split into three bf16 parts
+//           (hi + mid + lo, one accumulator); Im z / 2 pi is written as three signed base-512
+//           digits, each product summed in its own accumulator, so the phase is formed exactly
+//           modulo one turn from integer sums.  exp2/sin/cos on the FP32 transcendental unit; V
+//           (FP32) is split into three bf16 parts whose sum is exact for A3.
+//
+// The row shift M_k is the row maximum of the hi-part product plus w s (an approximation is
+// enough: any shift gives the same directions, and the true maximum term stays within e^{0.1}).
+#include <stdio.h>
+
+#include <type_traits>
+
+#include "hom_internal.h"
+
+namespace hom {
+
+typedef __bf16 bf16x8_t __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float f32x4_t __attribute__((__vector_size__(4 * sizeof(float))));
+typedef double f64x4_t __attribute__((__vector_size__(4 * sizeof(double))));
+
+constexpr int kDenseBlock = 256;       // 4 waves; each owns one 16-point tile at a time
+constexpr int64_t kDenseChunk = 8192;  // points per evaluation + LU round of hom_step
+
+__device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
+
+__device__ __forceinline__ bf16x8_t pack8(const uint32_t (&w)[4]) {
+  return __builtin_bit_cast(bf16x8_t, uint4{w[0], w[1], w[2], w[3]});
+}
+
+// two bf16-valued floats (low 16 bits zero) -> one packed register, a in the low half
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return (__float_as_uint(a) >> 16) | (__float_as_uint(b) & 0xffff0000u);
+}
+
+// round a float to its 8 most significant bits (nearest, ties to even; finite inputs)
+__device__ __forceinline__ float bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+// x ~ h + m + l, each exactly a bf16, residual below 2^-24 |x|
+__device__ __forceinline__ void split3_rne(double x, float &h, float &m, float &l) {
+  h = bf16_rne((float)x);
+  const double r = x - (double)h;
+  m = bf16_rne((float)r);
+  l = bf16_rne((float)(r - (double)m));
+}
+
+// v = h + m + l exactly (24 significant bits in three 8-bit pieces, by truncation)
+__device__ __forceinline__ void split3_exact(float v, float &h, float &m, float &l) {
+  h = __uint_as_float(__float_as_uint(v) & 0xffff0000u);
+  const float r = v - h;
+  m = __uint_as_float(__float_as_uint(r) & 0xffff0000u);
+  l = r - m;
+}
+
+// Im z / (2 pi), reduced to [-1/2, 1/2], as d1/512 + d2/512^2 + d3/512^3 with integer digits
+// |d| <= 256 (exact bf16 values); the dropped remainder is below 2^-28 turns.
+__device__ __forceinline__ void turn_digits(double im, float &d1, float &d2, float &d3) {
+  double t = im * kInv2Pi;
+  t -= rint(t);
+  const double t1 = t * 512.0;
+  const double r1 = rint(t1);
+  const double t2 = (t1 - r1) * 512.0;
+  const double r2 = rint(t2);
+  const double r3 = rint((t2 - r2) * 512.0);
+  d1 = (float)r1;
+  d2 = (float)r2;
+  d3 = (float)r3;
+}
+
+__device__ __forceinline__ f32x4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f64x4_t mfma_f64(double a, double b, f64x4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Coordinates of this lane's point in the bf16 B-operand layout (coordinates 8q .. 8q+7):
+// hi part of Re z only (the row-maximum pass).
+__device__ __forceinline__ void load_hi(const double *__restrict__ z, int64_t p, bool valid, int n,
+                                        int q, uint32_t (&zh)[4]) {
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    float h[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = 8 * q + e + u;
+      const double x = (valid && j < n) ? z[2 * (p * n + j)] : 0.0;
+      h[u] = bf16_rne((float)x);
+    }
+    zh[e / 2] = pack2(h[0], h[1]);
+  }
+}
+
+// Row maximum (pass 1) of equation tiles [t0, t1) for this lane's point, reduced over the wave's
+// four lane quarters (the same point).
+__device__ __forceinline__ float row_max(const DenseDev &D, int t0, int t1, int lane, int q,
+                                         const bf16x8_t zh, float sf) {
+  float m = -INFINITY;
+  const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int t = t0; t < t1; ++t) {
+    const f32x4_t d = mfma_bf16(as_bf16x8(D.EAb[t * 64 + lane]), zh, zero);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m = fmaxf(m, fmaf((float)D.W[t * 16 + 4 * q + r], sf, d[r]));
+  }
+  m = fmaxf(m, __shfl_xor(m, 16));
+  m = fmaxf(m, __shfl_xor(m, 32));
+  return m;
+}
+
+// e^{-z_j} of point p (the HOM_AFFINE column factor), or 0 outside the points and columns
+__device__ __forceinline__ Cx<double> affine_factor(const double *__restrict__ z, int64_t p,
+                                                    int64_t p1, int n, int j) {
+  if (p >= p1 || j >= n) return {0.0, 0.0};
+  double sn, cs;
+  sincos(-z[2 * (p * n + j) + 1], &sn, &cs);
+  const double mag = exp(-z[2 * (p * n + j)]);
+  return {mag * cs, mag * sn};
+}
+
+// Store row k of G for the tile.  acc*: J_z entries in the MFMA result layout (point 4q + r,
+// column 16 ct + c16); H, Hs: this lane's point c16; m: the row shift of point c16.
+template <typename OutT, typename AccT>
+__device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restrict__ logscale,
+                                          int flags, int64_t p0, int64_t pb, int64_t p1, int n,
+                                          int nct, int k, int q, int c16, const AccT (&aR)[2],
+                                          const AccT (&aI)[2], Cx<double> H, Cx<double> Hs,
+                                          double m, double sp, const double *__restrict__ z) {
+  const int ld = n + 2;
+  if (nct > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t p = pb + 4 * q + r;
+      const double mp = __shfl(m, 4 * q + r);
+      const double scale = (flags & 1) ? exp(mp) : 1.0;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const int col = 16 * ct + c16;
+        if (ct < nct && p < p1 && col < n) {
+          Cx<double> v = {(double)aR[ct][r] * scale, (double)aI[ct][r] * scale};
+          if (flags & 2) v = cmul(v, affine_factor(z, p, p1, n, col));
+          OutT *g = G + 2 * (((p - p0) * n + k) * ld + col);
+          g[0] = (OutT)v.x;
+          g[1] = (OutT)v.y;
+        }
+      }
+    }
+  }
+  const int64_t p = pb + c16;
+  if (q == 0 && p < p1) {
+    const double scale = (flags & 1) ? exp(m) : 1.0;
+    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // H_t = e^{-s} H_s
+    OutT *g = G + 2 * (((p - p0) * n + k) * ld + n);
+    g[0] = (OutT)(Hs.x * fs);
+    g[1] = (OutT)(Hs.y * fs);
+    g[2] = (OutT)(H.x * scale);
+    g[3] = (OutT)(H.y * scale);
+    if (logscale) logscale[p * n + k] = (flags & 1) ? 0.0 : m;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16x3 engine
+// ------------------------------------------------------------------------------------------
+template <typename OutT>
+__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2)))
+    k_dense_bf16(DenseDev D, const Cx<float> *__restrict__ Cf, int64_t p0, int64_t p1,
+                 const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
+                 double *__restrict__ logscale, int flags, unsigned long long *units) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int n = D.n, nct = D.nct;
+  const int64_t ntile = (p1 - p0 + 15) >> 4;
+  const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile;
+       tile += (int64_t)gridDim.x * 4) {
+    const int64_t pb = p0 + tile * 16, pl = pb + c16;
+    const bool lv = pl < p1;
+    // B operands: lane (c16, q) holds coordinates 8q .. 8q+7 of point c16
+    uint32_t zh[4], zm[4], zl[4], th[4], tm[4], tl[4];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      float h[2], m[2], l[2], a[2], b[2], c[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int j = 8 * q + e + u;
+        double xr = 0.0, xi = 0.0;
+        if (lv && j < n) {
+          xr = z[2 * (pl * n + j)];
+          xi = z[2 * (pl * n + j) + 1];
+        }
+        split3_rne(xr, h[u], m[u], l[u]);
+        turn_digits(xi, a[u], b[u], c[u]);
+      }
+      zh[e / 2] = pack2(h[0], h[1]);
+      zm[e / 2] = pack2(m[0], m[1]);
+      zl[e / 2] = pack2(l[0], l[1]);
+      th[e / 2] = pack2(a[0], a[1]);
+      tm[e / 2] = pack2(b[0], b[1]);
+      tl[e / 2] = pack2(c[0], c[1]);
+    }
+    const bf16x8_t Bzh = pack8(zh), Bzm = pack8(zm), Bzl = pack8(zl);
+    const bf16x8_t Bth = pack8(th), Btm = pack8(tm), Btl = pack8(tl);
+    const double sp = lv ? s[pl] : 0.0;
+    const float sf = (float)sp;
+
+    for (int k = 0; k < n; ++k) {
+      const int t0 = D.tile0[k], t1 = D.tile0[k + 1];
+      const float mk = row_max(D, t0, t1, lane, q, Bzh, sf);
+      const double Mk = (double)mk;
+      f32x4_t aR[2] = {zero, zero}, aI[2] = {zero, zero};
+      float hr = 0.f, hi = 0.f, sr = 0.f, si = 0.f;
+#pragma unroll 1
+      for (int ch = t0 >> 1; ch < (t1 >> 1); ++ch) {
+        uint32_t vr[3][4], vi[3][4];  // bf16 parts hi / mid / lo of V, packed in pairs
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int t = 2 * ch + hh;
+          const bf16x8_t ea = as_bf16x8(D.EAb[t * 64 + lane]);
+          f32x4_t dr = mfma_bf16(ea, Bzl, zero);
+          dr = mfma_bf16(ea, Bzm, dr);
+          dr = mfma_bf16(ea, Bzh, dr);
+          const f32x4_t d1 = mfma_bf16(ea, Bth, zero);
+          const f32x4_t d2 = mfma_bf16(ea, Btm, zero);
+          const f32x4_t d3 = mfma_bf16(ea, Btl, zero);
+          float Vr[4], Vi[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = t * 16 + 4 * q + r;
+            const double w = D.W[i];
+            const float e = dr[r] + (float)fma(w, sp, -Mk);
+            const float mag = __builtin_amdgcn_exp2f(e * (float)kLog2e);
+            // phase in turns from the exact digit sums: fract(d1/512 + d2/512^2) + d3/512^3
+            float ph = __builtin_amdgcn_fractf(d1[r] * (1.0f / 512.0f));
+            ph = __builtin_amdgcn_fractf(fmaf(d2[r], 1.0f / 262144.0f, ph));
+            ph = fmaf(d3[r], 1.0f / 134217728.0f, ph);
+            const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+            const Cx<float> cc = Cf[i];
+            const float cr = cc.x * mag, ci = cc.y * mag;
+            Vr[r] = cr * cs - ci * sn;
+            Vi[r] = cr * sn + ci * cs;
+            const float wf = (float)w;
+            hr += Vr[r];
+            hi += Vi[r];
+            sr = fmaf(wf, Vr[r], sr);
+            si = fmaf(wf, Vi[r], si);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            float a0, b0, c0, a1, b1, c1;
+            split3_exact(Vr[r], a0, b0, c0);
+            split3_exact(Vr[r + 1], a1, b1, c1);
+            vr[0][2 * hh + r / 2] = pack2(a0, a1);
+            vr[1][2 * hh + r / 2] = pack2(b0, b1);
+            vr[2][2 * hh + r / 2] = pack2(c0, c1);
+            split3_exact(Vi[r], a0, b0, c0);
+            split3_exact(Vi[r + 1], a1, b1, c1);
+            vi[0][2 * hh + r / 2] = pack2(a0, a1);
+            vi[1][2 * hh + r / 2] = pack2(b0, b1);
+            vi[2][2 * hh + r / 2] = pack2(c0, c1);
+          }
+        }
+        const bf16x8_t r0 = pack8(vr[0]), r1 = pack8(vr[1]), r2 = pack8(vr[2]);
+        const bf16x8_t i0 = pack8(vi[0]), i1 = pack8(vi[1]), i2 = pack8(vi[2]);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          if (ct < nct) {
+            const bf16x8_t cb = as_bf16x8(D.CBb[(ch * 2 + ct) * 64 + lane]);
+            aR[ct] = mfma_bf16(r2, cb, aR[ct]);
+            aR[ct] = mfma_bf16(r1, cb, aR[ct]);
+            aR[ct] = mfma_bf16(r0, cb, aR[ct]);
+            aI[ct] = mfma_bf16(i2, cb, aI[ct]);
+            aI[ct] = mfma_bf16(i1, cb, aI[ct]);
+            aI[ct] = mfma_bf16(i0, cb, aI[ct]);
+          }
+        }
+      }
+      hr += __shfl_xor(hr, 16);
+      hr += __shfl_xor(hr, 32);
+      hi += __shfl_xor(hi, 16);
+      hi += __shfl_xor(hi, 32);
+      sr += __shfl_xor(sr, 16);
+      sr += __shfl_xor(sr, 32);
+      si += __shfl_xor(si, 16);
+      si += __shfl_xor(si, 32);
+      store_row<OutT, f32x4_t>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI,
+                               Cx<double>{hr, hi}, Cx<double>{sr, si}, Mk, sp, z);
+    }
+    if (units && lane == 0) {
+      const int64_t cnt = p1 - pb < 16 ? p1 - pb : 16;
+      atomicAdd(units, (unsigned long long)cnt);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 engine
+// ------------------------------------------------------------------------------------------
+template <typename OutT>
+__global__ void __launch_bounds__(kDenseBlock)
+    k_dense_f64(DenseDev D, const Cx<double> *__restrict__ Cd, int64_t p0, int64_t p1,
+                const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
+                double *__restrict__ logscale, int flags, unsigned long long *units) {
+  const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  const int n = D.n, nct = D.nct, nks = D.nks;
+  const int64_t ntile = (p1 - p0 + 15) >> 4;
+  const f64x4_t zero = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile;
+       tile += (int64_t)gridDim.x * 4) {
+    const int64_t pb = p0 + tile * 16, pl = pb + c16;
+    const bool lv = pl < p1;
+    uint32_t zh[4];
+    load_hi(z, pl, lv, n, q, zh);
+    const bf16x8_t Bzh = pack8(zh);
+    // FP64 B operands: lane (c16, q) holds coordinate q + 4 ks of point c16; Im as turns
+    double zr[8], zt[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int j = q + 4 * ks;
+      double xr = 0.0, t = 0.0;
+      if (lv && j < n) {
+        xr = z[2 * (pl * n + j)];
+        t = z[2 * (pl * n + j) + 1] * kInv2Pi;
+        t -= rint(t);
+      }
+      zr[ks] = xr;
+      zt[ks] = t;
+    }
+    const double sp = lv ? s[pl] : 0.0;
+    const float sf = (float)sp;
+
+    for (int k = 0; k < n; ++k) {
+      const int t0 = D.tile0[k], t1 = D.tile0[k + 1];
+      const double Mk = (double)row_max(D, t0, t1, lane, q, Bzh, sf);
+      f64x4_t aR[2] = {zero, zero}, aI[2] = {zero, zero};
+      Cx<double> H = {0.0, 0.0}, Hs = {0.0, 0.0};
+#pragma unroll 1
+      for (int t = t0; t < t1; ++t) {
+        f64x4_t dr = zero, di = zero;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          if (ks < nks) {
+            const double ea = D.EAd[(t * 8 + ks) * 64 + lane];
+            dr = mfma_f64(ea, zr[ks], dr);
+            di = mfma_f64(ea, zt[ks], di);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = t * 16 + 4 * q + r;
+          const double w = D.W[i];
+          const double mag = exp(fma(w, sp, dr[r] - Mk));
+          const double ph = di[r] - rint(di[r]);
+          double sn, cs;
+          sincospi(2.0 * ph, &sn, &cs);
+          const Cx<double> cc = Cd[i];
+          const double cr = cc.x * mag, ci = cc.y * mag;
+          const double vr = cr * cs - ci * sn, vi = cr * sn + ci * cs;
+          H.x += vr;
+          H.y += vi;
+          Hs.x = fma(w, vr, Hs.x);
+          Hs.y = fma(w, vi, Hs.y);
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            if (ct < nct) {
+              const double cb = D.CBd[((t * 4 + r) * 2 + ct) * 64 + lane];
+              aR[ct] = mfma_f64(vr, cb, aR[ct]);
+              aI[ct] = mfma_f64(vi, cb, aI[ct]);
+            }
+          }
+        }
+      }
+      H.x += __shfl_xor(H.x, 16);
+      H.x += __shfl_xor(H.x, 32);
+      H.y += __shfl_xor(H.y, 16);
+      H.y += __shfl_xor(H.y, 32);
+      Hs.x += __shfl_xor(Hs.x, 16);
+      Hs.x += __shfl_xor(Hs.x, 32);
+      Hs.y += __shfl_xor(Hs.y, 16);
+      Hs.y += __shfl_xor(Hs.y, 32);
+      store_row<OutT, f64x4_t>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI, H, Hs,
+                               Mk, sp, z);
+    }
+    if (units && lane == 0) {
+      const int64_t cnt = p1 - pb < 16 ? p1 - pb : 16;
+      atomicAdd(units, (unsigned long long)cnt);
+    }
+  }
+}
+
+// Coefficients in the padded dense order (padding monomials get 0), FP64 and FP32 copies.
+__global__ void k_dense_coeffs(DenseDev D, const double *__restrict__ c, Cx<double> *__restrict__ Cd,
+                               Cx<float> *__restrict__ Cf) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D.Md; i += gridDim.x * blockDim.x) {
+    const int q = D.src[i];
+    Cx<double> v = {0.0, 0.0};
+    if (q >= 0) v = {c[2 * q], c[2 * q + 1]};
+    Cd[i] = v;
+    Cf[i] = {(float)v.x, (float)v.y};
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// A5 after a dense evaluation: the consolidated LU on rows read back from the chunk workspace.
+// Mixed form: FP32 rows and LU; a point whose FP32 pivot ratio is below 1e-4 (or singular) is
+// evaluated again on the vector units in FP64 and solved in FP64, as in the fused step.
+// ------------------------------------------------------------------------------------------
+template <int N, bool MIXED>
+__global__ void __launch_bounds__(kDenseBlock)
+    k_dense_lu(SysDev sd, const double *__restrict__ c, int64_t p0, int64_t p1,
+               const void *__restrict__ Gws, const double *__restrict__ z,
+               const double *__restrict__ s, double *__restrict__ dE, double *__restrict__ dN,
+               int32_t *__restrict__ status) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  extern __shared__ __align__(16) char smem[];
+  SysLds<N> S{};
+  if constexpr (MIXED) S = stage_tables<N>(smem, sd, c);
+  const T *Gw = static_cast<const T *>(Gws);
+  const Geo<N> geo;
+  const int n = sd.n, r = geo.r, ld = n + 2;
+  const int64_t gpb = (kDenseBlock / 64) * Geo<N>::G;
+  const int64_t stride = (int64_t)gridDim.x * gpb;
+  const int64_t q0 = p0 + (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g;
+  for (int64_t it = 0;; ++it) {
+    const int64_t p = q0 + it * stride;
+    const bool act = geo.valid && p < p1;
+    if (!__any(act)) break;
+    Cx<T> row[N + 2];
+#pragma unroll
+    for (int j = 0; j < N + 2; ++j) row[j] = {T(0), T(0)};
+    if (act && r < n) {
+      const T *g = Gw + 2 * ((p - p0) * n + r) * ld;
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j < n) row[j] = {g[2 * j], g[2 * j + 1]};
+      row[N] = {g[2 * n], g[2 * n + 1]};
+      row[N + 1] = {g[2 * n + 2], g[2 * n + 3]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j == r) row[j].x = T(1);
+    }
+    Cx<T> ef, qf;
+    double nE, nN;
+    T rf;
+    bool sing = lu_solve2<N, T>(row, r, geo.base, n, ef, qf, nE, nN, rf);
+    Cx<double> e = {(double)ef.x, (double)ef.y}, qv = {(double)qf.x, (double)qf.y};
+    double ratio = (double)rf;
+    if constexpr (MIXED) {
+      const bool redo = act && (sing || !(rf >= 1e-4f));
+      if (__any(redo)) {
+        double zr[N], zi[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          zr[j] = (redo && j < n) ? z[2 * (p * n + j)] : 0.0;
+          zi[j] = (redo && j < n) ? z[2 * (p * n + j) + 1] : 0.0;
+        }
+        const double sp = redo ? s[p] : 0.0;
+        Cx<double> rowd[N + 2], ed, qd;
+        double M, ad, rd, nEd, nNd;
+        eval_row_exact<N, double>(S, r, zr, zi, sp, rowd, M, ad);
+        const bool sd2 = lu_solve2<N, double>(rowd, r, geo.base, n, ed, qd, nEd, nNd, rd);
+        if (redo) {
+          e = ed;
+          qv = qd;
+          sing = sd2;
+          ratio = rd;
+        }
+      }
+    }
+    if (act) {
+      if (r < n) {
+        dE[2 * (p * n + r)] = e.x;
+        dE[2 * (p * n + r) + 1] = e.y;
+        dN[2 * (p * n + r)] = qv.x;
+        dN[2 * (p * n + r) + 1] = qv.y;
+      }
+      if (r == 0) status[p] = (sing || !(ratio >= 1e-14)) ? -1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t dense_ws_bytes(const System &S, int64_t P, bool step, int engine) {
+  size_t b = align256((size_t)S.Md * 16) + align256((size_t)S.Md * 8);
+  if (step) {
+    const int64_t pc = P < kDenseChunk ? P : kDenseChunk;
+    b += align256((size_t)pc * S.n * (S.n + 2) * (engine == 1 ? 8 : 16));
+  }
+  return b;
+}
+
+static int dense_grid(int64_t npts) {
+  const int64_t tiles = (npts + 15) / 16;
+  const int64_t need = (tiles + 3) / 4;
+  const int64_t cap = (int64_t)num_cus() * 8;
+  return (int)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+static hipError_t dense_coeffs(const System &S, const double *c, void *dws, Cx<double> **Cd,
+                               Cx<float> **Cf, hipStream_t stream) {
+  char *base = static_cast<char *>(dws);
+  *Cd = reinterpret_cast<Cx<double> *>(base);
+  *Cf = reinterpret_cast<Cx<float> *>(base + align256((size_t)S.Md * 16));
+  hipLaunchKernelGGL(k_dense_coeffs, dim3((S.Md + 255) / 256), dim3(256), 0, stream, S.dense, c,
+                     *Cd, *Cf);
+  return hipGetLastError();
+}
+
+template <typename OutT>
+static void dense_launch(const System &S, int engine, const Cx<double> *Cd, const Cx<float> *Cf,
+                         int64_t p0, int64_t p1, const double *z, const double *s, OutT *G,
+                         double *logscale, int flags, hipStream_t stream) {
+  prof_begin(stream);
+  unsigned long long *units = prof_units(stream);
+  const dim3 grid(dense_grid(p1 - p0)), block(kDenseBlock);
+  if (engine == 1)
+    hipLaunchKernelGGL((k_dense_bf16<OutT>), grid, block, 0, stream, S.dense, Cf, p0, p1, z, s, G,
+                       logscale, flags, units);
+  else
+    hipLaunchKernelGGL((k_dense_f64<OutT>), grid, block, 0, stream, S.dense, Cd, p0, p1, z, s, G,
+                       logscale, flags, units);
+  prof_end(stream, engine == 1 ? "k_dense<bf16x3>" : "k_dense<fp64>");
+}
+
+hipError_t launch_dense_eval(const System &S, const double *c, int64_t P, const double *z,
+                             const double *s, double *G, double *logscale, int flags, int engine,
+                             void *dws, hipStream_t stream) {
+  Cx<double> *Cd;
+  Cx<float> *Cf;
+  hipError_t e = dense_coeffs(S, c, dws, &Cd, &Cf, stream);
+  if (e != hipSuccess) return e;
+  dense_launch<double>(S, engine, Cd, Cf, 0, P, z, s, G, logscale, flags, stream);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t dense_lu_n(const System &S, const void *cws, const double *c, int64_t p0,
+                             int64_t p1, const void *Gws, const double *z, const double *s,
+                             double *dE, double *dN, int32_t *status, bool mixed,
+                             hipStream_t stream) {
+  const int gpb = (kDenseBlock / 64) * Geo<N>::G;
+  const int64_t need = (p1 - p0 + gpb - 1) / gpb;
+  const int64_t cap = (int64_t)num_cus() * 8;
+  const dim3 grid((unsigned)(need < cap ? need : cap)), block(kDenseBlock);
+  char label[64];
+  snprintf(label, sizeof label, "k_dense_lu<%d,%s>", N, mixed ? "mixed" : "fp64");
+  prof_begin(stream);
+  if (mixed)
+    hipLaunchKernelGGL((k_dense_lu<N, true>), grid, block, S.lds_bytes, stream, S.dev(cws), c, p0,
+                       p1, Gws, z, s, dE, dN, status);
+  else
+    hipLaunchKernelGGL((k_dense_lu<N, false>), grid, block, 0, stream, S.dev(cws), c, p0, p1, Gws,
+                       z, s, dE, dN, status);
+  prof_end(stream, label);
+  return hipGetLastError();
+}
+
+#define HOM_SWITCH_D(N, CALL)                  \
+  switch (N) {                                 \
+    case 2: { constexpr int NN = 2; CALL; }    \
+    case 3: { constexpr int NN = 3; CALL; }    \
+    case 4: { constexpr int NN = 4; CALL; }    \
+    case 5: { constexpr int NN = 5; CALL; }    \
+    case 6: { constexpr int NN = 6; CALL; }    \
+    case 7: { constexpr int NN = 7; CALL; }    \
+    case 8: { constexpr int NN = 8; CALL; }    \
+    case 10: { constexpr int NN = 10; CALL; }  \
+    case 12: { constexpr int NN = 12; CALL; }  \
+    case 16: { constexpr int NN = 16; CALL; }  \
+    case 20: { constexpr int NN = 20; CALL; }  \
+    case 24: { constexpr int NN = 24; CALL; }  \
+    case 32: { constexpr int NN = 32; CALL; }  \
+    default: return hipErrorInvalidValue;      \
+  }
+
+hipError_t launch_dense_step(const System &S, const void *cws, const double *c, int64_t P,
+                             const double *z, const double *s, double *dE, double *dN,
+                             int32_t *status, int precision, void *dws, hipStream_t stream) {
+  const bool mixed = precision == 1;
+  const int engine = mixed ? 1 : 0;
+  Cx<double> *Cd;
+  Cx<float> *Cf;
+  hipError_t e = dense_coeffs(S, c, dws, &Cd, &Cf, stream);
+  if (e != hipSuccess) return e;
+  char *Gws = static_cast<char *>(dws) + align256((size_t)S.Md * 16) + align256((size_t)S.Md * 8);
+  for (int64_t p0 = 0; p0 < P; p0 += kDenseChunk) {
+    const int64_t p1 = P - p0 < kDenseChunk ? P : p0 + kDenseChunk;
+    if (mixed)
+      dense_launch<float>(S, engine, Cd, Cf, p0, p1, z, s, reinterpret_cast<float *>(Gws), nullptr,
+                          0, stream);
+    else
+      dense_launch<double>(S, engine, Cd, Cf, p0, p1, z, s, reinterpret_cast<double *>(Gws),
+                           nullptr, 0, stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    HOM_SWITCH_D(S.N, e = dense_lu_n<NN>(S, cws, c, p0, p1, Gws, z, s, dE, dN, status, mixed,
+                                         stream);
+                 break)
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace hom

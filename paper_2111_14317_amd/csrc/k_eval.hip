@@ -174,9 +174,35 @@ static int grid_for(int64_t P, int groups_per_block) {
     default: return hipErrorInvalidValue; \
   }
 
+// Table-order coefficients and their moduli [mmax][n] for a system whose tables stay in global
+// memory (the same arrays stage_tables builds in LDS otherwise).
+__global__ void k_coeff_tables(SysDev sd, const double *__restrict__ c, Cx<double> *__restrict__ C,
+                               double *__restrict__ Cabs) {
+  const int total = sd.mmax * sd.n;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int i = idx / sd.n, r = idx - i * sd.n;
+    Cx<double> v = {0.0, 0.0};
+    if (i < sd.mk[r]) {
+      const int q = sd.off[r] + i;
+      v.x = c[2 * q];
+      v.y = c[2 * q + 1];
+    }
+    C[idx] = v;
+    Cabs[idx] = sqrt(v.x * v.x + v.y * v.y);
+  }
+}
+
+hipError_t launch_coeff_tables(const System &S, const double *c, void *cws, hipStream_t stream) {
+  const SysDev sd = S.dev(cws);
+  const int total = S.mmax * S.n;
+  hipLaunchKernelGGL(k_coeff_tables, dim3((total + 255) / 256), dim3(256), 0, stream, sd, c,
+                     const_cast<Cx<double> *>(sd.Cg), const_cast<double *>(sd.Cabs_g));
+  return hipGetLastError();
+}
+
 template <int N>
-static hipError_t eval_n(const System &S, const double *c, int64_t P, const double *z,
-                         const double *s, double *G, double *logscale, int flags,
+static hipError_t eval_n(const System &S, const void *cws, const double *c, int64_t P,
+                         const double *z, const double *s, double *G, double *logscale, int flags,
                          hipStream_t stream) {
   const int gpb = (kBlock / 64) * Geo<N>::G;
   char label[64];
@@ -184,42 +210,42 @@ static hipError_t eval_n(const System &S, const double *c, int64_t P, const doub
   prof_begin(stream);
   if (flags & 4)
     hipLaunchKernelGGL((k_eval<N, float>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(), c, P, z, s, G, logscale, flags);
+                       stream, S.dev(cws), c, P, z, s, G, logscale, flags);
   else
     hipLaunchKernelGGL((k_eval<N, double>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(), c, P, z, s, G, logscale, flags);
+                       stream, S.dev(cws), c, P, z, s, G, logscale, flags);
   prof_end(stream, label);
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t step_n(const System &S, const double *c, int64_t P, const double *z,
-                         const double *s, double *dE, double *dN, int32_t *status,
-                         int precision, hipStream_t stream) {
+static hipError_t step_n(const System &S, const void *cws, const double *c, int64_t P,
+                         const double *z, const double *s, double *dE, double *dN,
+                         int32_t *status, int precision, hipStream_t stream) {
   const int gpb = (kBlock / 64) * Geo<N>::G;
   char label[64];
   snprintf(label, sizeof label, "k_step<%d,%s>", N, precision == 1 ? "mixed" : "fp64");
   prof_begin(stream);
   if (precision == 1)
     hipLaunchKernelGGL((k_step<N, true>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(), c, P, z, s, dE, dN, status);
+                       stream, S.dev(cws), c, P, z, s, dE, dN, status);
   else
     hipLaunchKernelGGL((k_step<N, false>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(), c, P, z, s, dE, dN, status);
+                       stream, S.dev(cws), c, P, z, s, dE, dN, status);
   prof_end(stream, label);
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const System &S, const double *c, int64_t P, const double *z,
-                       const double *s, double *G, double *logscale, int flags,
+hipError_t launch_eval(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z, const double *s, double *G, double *logscale, int flags,
                        hipStream_t stream) {
-  HOM_SWITCH(S.N, return eval_n<NN>(S, c, P, z, s, G, logscale, flags, stream))
+  HOM_SWITCH(S.N, return eval_n<NN>(S, cws, c, P, z, s, G, logscale, flags, stream))
 }
 
-hipError_t launch_step(const System &S, const double *c, int64_t P, const double *z,
-                       const double *s, double *dE, double *dN, int32_t *status, int precision,
-                       hipStream_t stream) {
-  HOM_SWITCH(S.N, return step_n<NN>(S, c, P, z, s, dE, dN, status, precision, stream))
+hipError_t launch_step(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z, const double *s, double *dE, double *dN,
+                       int32_t *status, int precision, hipStream_t stream) {
+  HOM_SWITCH(S.N, return step_n<NN>(S, cws, c, P, z, s, dE, dN, status, precision, stream))
 }
 
 }  // namespace hom

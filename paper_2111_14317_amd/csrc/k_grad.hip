@@ -147,7 +147,8 @@ size_t grad_work_elems(const System &S, int64_t P) {
 }
 
 template <int N>
-static hipError_t grad_n(const System &S, const double *c, int64_t P, const double *z,
+static hipError_t grad_n(const System &S, const void *cws, const double *c, int64_t P,
+                         const double *z,
                          const double *gx, double *grad, int precision, double *work,
                          size_t work_elems, hipStream_t stream) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
@@ -169,10 +170,10 @@ static hipError_t grad_n(const System &S, const double *c, int64_t P, const doub
     prof_begin(stream);
     if (precision == 1)
       hipLaunchKernelGGL((k_grad_paths<N, true>), dim3(blocks), dim3(64), tb + tile, stream,
-                         S.dev(), c, P0, pc, z, gx, work, tb);
+                         S.dev(cws), c, P0, pc, z, gx, work, tb);
     else
       hipLaunchKernelGGL((k_grad_paths<N, false>), dim3(blocks), dim3(64), tb + tile, stream,
-                         S.dev(), c, P0, pc, z, gx, work, tb);
+                         S.dev(cws), c, P0, pc, z, gx, work, tb);
     prof_end(stream, label);
     hipLaunchKernelGGL(k_grad_red1, dim3((S.M + 255) / 256, kRedT), dim3(256), 0, stream, work,
                        pc, S.M, kRedT, part);
@@ -200,10 +201,11 @@ static hipError_t grad_n(const System &S, const double *c, int64_t P, const doub
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_grad(const System &S, const double *c, int64_t P, const double *z_end,
+hipError_t launch_grad(const System &S, const void *cws, const double *c, int64_t P,
+                       const double *z_end,
                        const double *grad_x, double *grad_c, int precision, double *work,
                        size_t work_elems, hipStream_t stream) {
-  HOM_SWITCH_G(S.N, return grad_n<NN>(S, c, P, z_end, grad_x, grad_c, precision, work,
+  HOM_SWITCH_G(S.N, return grad_n<NN>(S, cws, c, P, z_end, grad_x, grad_c, precision, work,
                                       work_elems, stream))
 }
 

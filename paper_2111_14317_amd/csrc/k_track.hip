@@ -389,9 +389,10 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
 template <int N>
-static hipError_t track_n(const System &S, const double *c, int64_t P, double *z, double *s,
-                          double *ds, int32_t *status, int32_t *counters, const TrackDev &pr,
-                          bool mixed, unsigned long long *queue, hipStream_t stream) {
+static hipError_t track_n(const System &S, const void *cws, const double *c, int64_t P, double *z,
+                          double *s, double *ds, int32_t *status, int32_t *counters,
+                          const TrackDev &pr, bool mixed, unsigned long long *queue,
+                          hipStream_t stream) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
   const size_t lds = tb + track_state_bytes<N>();
   auto kern = mixed ? k_track<N, true> : k_track<N, false>;
@@ -408,7 +409,7 @@ static hipError_t track_n(const System &S, const double *c, int64_t P, double *z
   snprintf(label, sizeof label, "k_track<%d,%s>", N, mixed ? "mixed" : "fp64");
   prof_begin(stream);
   unsigned long long *units = prof_units(stream);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kTrackBlock), lds, stream, S.dev(), c,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kTrackBlock), lds, stream, S.dev(cws), c,
                      P, z, s, ds, status, counters, pr, queue, tb, units);
   prof_end(stream, label);
   return hipGetLastError();
@@ -432,11 +433,12 @@ static hipError_t track_n(const System &S, const double *c, int64_t P, double *z
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_track(const System &S, const double *c, int64_t P, double *z, double *s,
-                        double *ds, int32_t *status, int32_t *counters, const TrackDev &pr,
-                        bool mixed, unsigned long long *queue, hipStream_t stream) {
-  HOM_SWITCH_T(S.N, return track_n<NN>(S, c, P, z, s, ds, status, counters, pr, mixed, queue,
-                                       stream))
+hipError_t launch_track(const System &S, const void *cws, const double *c, int64_t P, double *z,
+                        double *s, double *ds, int32_t *status, int32_t *counters,
+                        const TrackDev &pr, bool mixed, unsigned long long *queue,
+                        hipStream_t stream) {
+  HOM_SWITCH_T(S.N, return track_n<NN>(S, cws, c, P, z, s, ds, status, counters, pr, mixed,
+                                       queue, stream))
 }
 
 // ------------------------------------------------------------------------------------------
