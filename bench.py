@@ -38,6 +38,40 @@ PEAK_FP64 = 78.6e12
 PEAK_FP32 = 157.3e12
 
 
+# HBM traffic of the dominant kernel comes from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE),
+# summarised in this file together with a hash of the kernel's sources; it is reported only while
+# the sources still hash to the same value (after a kernel change the counters are stale).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_track_n10_mixed_hbm.txt")
+KERNEL_SOURCES = ["paper_2111_14317_amd/csrc/k_track.hip", "paper_2111_14317_amd/csrc/hom_device.h",
+                  "paper_2111_14317_amd/csrc/hom_internal.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the mixed tracker (fetch + write, calibrated), or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _peak_mixed():
     # time lower bound: FP64 part at the FP64 peak, the rest at the FP32 peak
     t = FP64_SHARE / PEAK_FP64 + (FLOPS_PER_UNIT - FP64_SHARE) / PEAK_FP32
@@ -205,7 +239,7 @@ def main():
                     help="skip the dense-support (n=32, m=128) eval/step leg")
     ap.add_argument("--dense-points", type=int, default=262144)
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run one plain 512 MiB device-to-device copy (scales HBM counters)")
+                    help="also write and then read one 512 MiB buffer (scales the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
@@ -217,14 +251,14 @@ def main():
     import paper_2111_14317_amd as hom
     csys, z0 = _workload(args.paths)
     h = hom.System.from_workload(csys)
-    if args.copy_calib:
-        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        src.fill_(1)
+    if args.copy_calib:  # known traffic for scaling the HBM counters: write 512 MiB, read 512 MiB
+        buf = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        buf.fill_(1)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        total = int(torch.sum(buf, dtype=torch.int64))
         torch.cuda.synchronize()
-        del src, dst
+        assert total == 512 << 20
+        del buf
     res = {}
     for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
         res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup)
@@ -239,7 +273,7 @@ def main():
         achieved = dom_units * FLOPS_PER_UNIT / (dom_ms * 1e-3)
         peak = _peak_mixed()
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": dom, "kernel_ms": dom_ms,
+                "frac": achieved / peak, "traffic": measured_traffic(), "kernel": dom, "kernel_ms": dom_ms,
                 "kernel_units": dom_units, "flops_per_unit": FLOPS_PER_UNIT}
     f64 = res["fp64"]
     f64_dom = f"k_track<{N_EQ},fp64>"

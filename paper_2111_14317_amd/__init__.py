@@ -164,6 +164,7 @@ class Batch(System):
         self.handle = h
         self.n = max(ns)
         self.ns = ns
+        self.mmax = [int(np.max(sy.m)) for sy in systems]
         self.num_sys = len(systems)
         self.M = int(sum(int(np.sum(sy.m)) for sy in systems))
 

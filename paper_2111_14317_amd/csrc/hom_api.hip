@@ -211,10 +211,10 @@ static void build_dense(int n, const int32_t *m, const int8_t *A, const double *
         D.EAb[((size_t)t * 64 + l) * 8 + e] = bf16_of_int(a(16 * t + l % 16, 8 * (l / 16) + e));
       for (int ks = 0; ks < 8; ++ks)  // A1 FP64 A operand
         D.EAd[((size_t)t * 8 + ks) * 64 + l] = a(16 * t + l % 16, 4 * ks + l / 16);
-      for (int r = 0; r < 4; ++r)  // A3 FP64 B operand: K = monomial 4(l/16) + r of the tile
-        for (int ct = 0; ct < 2; ++ct)
+      for (int r = 0; r < 4; ++r)  // A3 FP64 B operand: K = monomial 4r + l/16 of the tile (the
+        for (int ct = 0; ct < 2; ++ct)  // row that result register r of lane l holds after A1)
           D.CBd[(((size_t)t * 4 + r) * 2 + ct) * 64 + l] =
-              a(16 * t + 4 * (l / 16) + r, 16 * ct + l % 16);
+              a(16 * t + 4 * r + l / 16, 16 * ct + l % 16);
     }
   for (int ch = 0; ch < Md / 32; ++ch)  // A3 bf16 B operand: element e of K block l/16 is
     for (int ct = 0; ct < 2; ++ct)      // monomial 32 ch + 16 (e / 4) + 4 (l / 16) + e % 4
@@ -569,7 +569,7 @@ static TrackDev to_dev(const hom_track_params *p) {
   return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
                   p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
                   p->max_newton, p->max_end,    p->max_steps, p->max_iters,
-                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile};
+                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3};
 }
 
 int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
@@ -594,13 +594,19 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, "hom_track: NULL array");
   hipStream_t st = (hipStream_t)stream;
   const TrackDev pr = to_dev(params);
+  const bool mixed = params->precision == HOM_MIXED;
+  // The mixed form runs two launches: FP32 tracking of fresh and running paths (which parks the
+  // paths that need FP64, and every endgame), then FP64 for the parked paths.
+  TrackDev pr64 = pr;
+  pr64.claim = 4 | 8;
   hipError_t e = hipSuccess;
   if (batch) {
     // workspace: queue counter, per-system path and item offsets, table-order coefficients
     void *ws = nullptr;
     HOM_HIP(hipMallocAsync(&ws, track_batch_ws_bytes(h->s), st), "hom_track: workspace");
-    e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr,
-                           params->precision == HOM_MIXED, ws, st);
+    e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr, mixed, ws, st);
+    if (e == hipSuccess && mixed)
+      e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr64, false, ws, st);
     hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) HOM_HIP(e, "hom_track");
     HOM_HIP(e2, "hom_track: free workspace");
@@ -612,8 +618,9 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   void *cws = nullptr;
   e = coeff_begin(h->s, c, st, &cws);
   if (e == hipSuccess)
-    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr,
-                     params->precision == HOM_MIXED, queue, st);
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr, mixed, queue, st);
+  if (e == hipSuccess && mixed)
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
   hipError_t e2 = coeff_end(cws, st);
   hipError_t e3 = hipFreeAsync(queue, st);
   HOM_HIP(e, "hom_track");

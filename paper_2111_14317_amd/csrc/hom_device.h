@@ -157,10 +157,11 @@ __host__ __device__ constexpr size_t lds_table_bytes(int n, int mmax) {
 }
 
 // Cooperative copy of the tables into LDS (whole block).  c: complex128 [M] equation-major.
-// For a system whose tables stay in global memory this only returns the global pointers.
-template <int N>
+// GT (tables in global memory): only return the global pointers.  A compile-time choice, so
+// that the evaluation's table reads compile to LDS instructions when the tables are staged.
+template <int N, bool GT>
 __device__ SysLds<N> stage_tables(char *smem, const SysDev &sd, const double *__restrict__ c) {
-  if (sd.Cg) return SysLds<N>{sd.T, sd.Cg, sd.Cabs_g, sd.mk, sd.n, sd.mmax};
+  if constexpr (GT) return SysLds<N>{sd.T, sd.Cg, sd.Cabs_g, sd.mk, sd.n, sd.mmax};
   constexpr int LD = TableLD<N>::value;
   const int n = sd.n, mmax = sd.mmax;
   double *sT = reinterpret_cast<double *>(smem);

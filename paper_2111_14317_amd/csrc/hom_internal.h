@@ -82,6 +82,8 @@ struct TrackDev {
   int max_polish, max_newton, max_end, max_steps, max_iters;
   int exact_shift;
   int tile;
+  int claim;  // statuses a launch takes up: bit 0 fresh (1), bit 1 running (2), bit 2 parked
+              // (3), bit 3 parked for the endgame (4)
 };
 
 

@@ -32,7 +32,9 @@ typedef float f32x4_t __attribute__((__vector_size__(4 * sizeof(float))));
 typedef double f64x4_t __attribute__((__vector_size__(4 * sizeof(double))));
 
 constexpr int kDenseBlock = 256;       // 4 waves; each owns one 16-point tile at a time
-constexpr int64_t kDenseChunk = 8192;  // points per evaluation + LU round of hom_step
+// points per evaluation + LU round of hom_step: 4096 tiles, enough blocks for every CU; the FP32
+// rows of a round take 570 MB at n = 32
+constexpr int64_t kDenseChunk = 65536;
 
 __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
 
@@ -83,6 +85,11 @@ __device__ __forceinline__ void turn_digits(double im, float &d1, float &d2, flo
   d3 = (float)r3;
 }
 
+// Result layouts of the two 16x16 MFMA shapes: lane l holds column l % 16; its four result
+// registers r hold rows 4 (l / 16) + r (f32, 16x16x32 bf16) and 4 r + l / 16 (f64, 16x16x4 f64).
+__device__ __forceinline__ int row_f32(int q, int r) { return 4 * q + r; }
+__device__ __forceinline__ int row_f64(int q, int r) { return 4 * r + q; }
+
 __device__ __forceinline__ f32x4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f32x4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
@@ -118,7 +125,7 @@ __device__ __forceinline__ float row_max(const DenseDev &D, int t0, int t1, int 
   for (int t = t0; t < t1; ++t) {
     const f32x4_t d = mfma_bf16(as_bf16x8(D.EAb[t * 64 + lane]), zh, zero);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) m = fmaxf(m, fmaf((float)D.W[t * 16 + 4 * q + r], sf, d[r]));
+    for (int r = 0; r < 4; ++r) m = fmaxf(m, fmaf((float)D.W[t * 16 + row_f32(q, r)], sf, d[r]));
   }
   m = fmaxf(m, __shfl_xor(m, 16));
   m = fmaxf(m, __shfl_xor(m, 32));
@@ -135,9 +142,9 @@ __device__ __forceinline__ Cx<double> affine_factor(const double *__restrict__ z
   return {mag * cs, mag * sn};
 }
 
-// Store row k of G for the tile.  acc*: J_z entries in the MFMA result layout (point 4q + r,
+// Store row k of G for the tile.  acc*: J_z entries in the MFMA result layout (point row(q, r),
 // column 16 ct + c16); H, Hs: this lane's point c16; m: the row shift of point c16.
-template <typename OutT, typename AccT>
+template <typename OutT, typename AccT, bool F64>
 __device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restrict__ logscale,
                                           int flags, int64_t p0, int64_t pb, int64_t p1, int n,
                                           int nct, int k, int q, int c16, const AccT (&aR)[2],
@@ -147,8 +154,9 @@ __device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restri
   if (nct > 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t p = pb + 4 * q + r;
-      const double mp = __shfl(m, 4 * q + r);
+      const int pr = F64 ? row_f64(q, r) : row_f32(q, r);
+      const int64_t p = pb + pr;
+      const double mp = __shfl(m, pr);
       const double scale = (flags & 1) ? exp(mp) : 1.0;
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
@@ -242,7 +250,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
           float Vr[4], Vi[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = t * 16 + 4 * q + r;
+            const int i = t * 16 + row_f32(q, r);
             const double w = D.W[i];
             const float e = dr[r] + (float)fma(w, sp, -Mk);
             const float mag = __builtin_amdgcn_exp2f(e * (float)kLog2e);
@@ -299,7 +307,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       sr += __shfl_xor(sr, 32);
       si += __shfl_xor(si, 16);
       si += __shfl_xor(si, 32);
-      store_row<OutT, f32x4_t>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI,
+      store_row<OutT, f32x4_t, false>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI,
                                Cx<double>{hr, hi}, Cx<double>{sr, si}, Mk, sp, z);
     }
     if (units && lane == 0) {
@@ -352,18 +360,26 @@ __global__ void __launch_bounds__(kDenseBlock)
       Cx<double> H = {0.0, 0.0}, Hs = {0.0, 0.0};
 #pragma unroll 1
       for (int t = t0; t < t1; ++t) {
-        f64x4_t dr = zero, di = zero;
+        // two accumulator chains per product (even / odd K steps) so that consecutive MFMAs
+        // do not wait for each other's results
+        f64x4_t dr0 = zero, di0 = zero, dr1 = zero, di1 = zero;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
+        for (int ks = 0; ks < 8; ks += 2) {
           if (ks < nks) {
             const double ea = D.EAd[(t * 8 + ks) * 64 + lane];
-            dr = mfma_f64(ea, zr[ks], dr);
-            di = mfma_f64(ea, zt[ks], di);
+            dr0 = mfma_f64(ea, zr[ks], dr0);
+            di0 = mfma_f64(ea, zt[ks], di0);
+          }
+          if (ks + 1 < nks) {
+            const double ea = D.EAd[(t * 8 + ks + 1) * 64 + lane];
+            dr1 = mfma_f64(ea, zr[ks + 1], dr1);
+            di1 = mfma_f64(ea, zt[ks + 1], di1);
           }
         }
+        const f64x4_t dr = dr0 + dr1, di = di0 + di1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = t * 16 + 4 * q + r;
+          const int i = t * 16 + row_f64(q, r);
           const double w = D.W[i];
           const double mag = exp(fma(w, sp, dr[r] - Mk));
           const double ph = di[r] - rint(di[r]);
@@ -394,7 +410,7 @@ __global__ void __launch_bounds__(kDenseBlock)
       Hs.x += __shfl_xor(Hs.x, 32);
       Hs.y += __shfl_xor(Hs.y, 16);
       Hs.y += __shfl_xor(Hs.y, 32);
-      store_row<OutT, f64x4_t>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI, H, Hs,
+      store_row<OutT, f64x4_t, true>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI, H, Hs,
                                Mk, sp, z);
     }
     if (units && lane == 0) {
@@ -421,7 +437,7 @@ __global__ void k_dense_coeffs(DenseDev D, const double *__restrict__ c, Cx<doub
 // Mixed form: FP32 rows and LU; a point whose FP32 pivot ratio is below 1e-4 (or singular) is
 // evaluated again on the vector units in FP64 and solved in FP64, as in the fused step.
 // ------------------------------------------------------------------------------------------
-template <int N, bool MIXED>
+template <int N, bool MIXED, bool GT>
 __global__ void __launch_bounds__(kDenseBlock)
     k_dense_lu(SysDev sd, const double *__restrict__ c, int64_t p0, int64_t p1,
                const void *__restrict__ Gws, const double *__restrict__ z,
@@ -430,7 +446,7 @@ __global__ void __launch_bounds__(kDenseBlock)
   using T = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ __align__(16) char smem[];
   SysLds<N> S{};
-  if constexpr (MIXED) S = stage_tables<N>(smem, sd, c);
+  if constexpr (MIXED) S = stage_tables<N, GT>(smem, sd, c);
   const T *Gw = static_cast<const T *>(Gws);
   const Geo<N> geo;
   const int n = sd.n, r = geo.r, ld = n + 2;
@@ -566,12 +582,11 @@ static hipError_t dense_lu_n(const System &S, const void *cws, const double *c, 
   char label[64];
   snprintf(label, sizeof label, "k_dense_lu<%d,%s>", N, mixed ? "mixed" : "fp64");
   prof_begin(stream);
-  if (mixed)
-    hipLaunchKernelGGL((k_dense_lu<N, true>), grid, block, S.lds_bytes, stream, S.dev(cws), c, p0,
-                       p1, Gws, z, s, dE, dN, status);
-  else
-    hipLaunchKernelGGL((k_dense_lu<N, false>), grid, block, 0, stream, S.dev(cws), c, p0, p1, Gws,
-                       z, s, dE, dN, status);
+  const size_t tb = mixed ? (S.lds_bytes + 15) & ~(size_t)15 : 0;
+  auto kern = mixed ? (S.global_tables ? k_dense_lu<N, true, true> : k_dense_lu<N, true, false>)
+                    : k_dense_lu<N, false, false>;
+  hipLaunchKernelGGL(kern, grid, block, tb, stream, S.dev(cws), c, p0, p1, Gws, z, s, dE, dN,
+                     status);
   prof_end(stream, label);
   return hipGetLastError();
 }

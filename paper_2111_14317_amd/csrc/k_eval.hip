@@ -27,14 +27,14 @@ __device__ __forceinline__ void load_point(const double *__restrict__ z, int64_t
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, bool GT>
 __global__ void __launch_bounds__(kBlock) k_eval(SysDev sd, const double *__restrict__ c,
                                                  int64_t P, const double *__restrict__ z,
                                                  const double *__restrict__ s,
                                                  double *__restrict__ G,
                                                  double *__restrict__ logscale, int flags) {
   extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   const Geo<N> geo;
   if (!geo.valid) return;
   const int n = sd.n, r = geo.r;
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) k_eval(SysDev sd, const double *__rest
 
 // Evaluation + consolidated solve.  The loop over points is wave-uniform (the LU shuffles);
 // groups past the end compute on a dummy point and store nothing.
-template <int N, bool MIXED>
+template <int N, bool MIXED, bool GT>
 __global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__restrict__ c,
                                                  int64_t P, const double *__restrict__ z,
                                                  const double *__restrict__ s,
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__rest
                                                  double *__restrict__ dN,
                                                  int32_t *__restrict__ status) {
   extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   const Geo<N> geo;
   const int n = sd.n, r = geo.r;
   const int64_t gpb = (kBlock / 64) * Geo<N>::G;
@@ -208,12 +208,10 @@ static hipError_t eval_n(const System &S, const void *cws, const double *c, int6
   char label[64];
   snprintf(label, sizeof label, "k_eval<%d,%s>", N, (flags & 4) ? "fp32" : "fp64");
   prof_begin(stream);
-  if (flags & 4)
-    hipLaunchKernelGGL((k_eval<N, float>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(cws), c, P, z, s, G, logscale, flags);
-  else
-    hipLaunchKernelGGL((k_eval<N, double>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(cws), c, P, z, s, G, logscale, flags);
+  auto kern = (flags & 4) ? (S.global_tables ? k_eval<N, float, true> : k_eval<N, float, false>)
+                          : (S.global_tables ? k_eval<N, double, true> : k_eval<N, double, false>);
+  hipLaunchKernelGGL(kern, dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes, stream, S.dev(cws),
+                     c, P, z, s, G, logscale, flags);
   prof_end(stream, label);
   return hipGetLastError();
 }
@@ -226,12 +224,10 @@ static hipError_t step_n(const System &S, const void *cws, const double *c, int6
   char label[64];
   snprintf(label, sizeof label, "k_step<%d,%s>", N, precision == 1 ? "mixed" : "fp64");
   prof_begin(stream);
-  if (precision == 1)
-    hipLaunchKernelGGL((k_step<N, true>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(cws), c, P, z, s, dE, dN, status);
-  else
-    hipLaunchKernelGGL((k_step<N, false>), dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes,
-                       stream, S.dev(cws), c, P, z, s, dE, dN, status);
+  auto kern = precision == 1 ? (S.global_tables ? k_step<N, true, true> : k_step<N, true, false>)
+                             : (S.global_tables ? k_step<N, false, true> : k_step<N, false, false>);
+  hipLaunchKernelGGL(kern, dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes, stream, S.dev(cws), c,
+                     P, z, s, dE, dN, status);
   prof_end(stream, label);
   return hipGetLastError();
 }

@@ -17,7 +17,7 @@
 
 namespace hom {
 
-template <int N, bool MIXED>
+template <int N, bool MIXED, bool GT>
 __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__restrict__ c,
                                                    int64_t P0, int64_t Pc,
                                                    const double *__restrict__ z,
@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__re
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr int LD = TableLD<N>::value;
   extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   const Geo<N> geo;
   const int n = sd.n, r = geo.r, M = sd.M;
   Cx<T> *tile = reinterpret_cast<Cx<T> *>(smem + table_bytes) + (geo.valid ? geo.g : 0) * N * N;
@@ -168,12 +168,11 @@ static hipError_t grad_n(const System &S, const void *cws, const double *c, int6
     char label[64];
     snprintf(label, sizeof label, "k_grad_paths<%d,%s>", N, precision == 1 ? "mixed" : "fp64");
     prof_begin(stream);
-    if (precision == 1)
-      hipLaunchKernelGGL((k_grad_paths<N, true>), dim3(blocks), dim3(64), tb + tile, stream,
-                         S.dev(cws), c, P0, pc, z, gx, work, tb);
-    else
-      hipLaunchKernelGGL((k_grad_paths<N, false>), dim3(blocks), dim3(64), tb + tile, stream,
-                         S.dev(cws), c, P0, pc, z, gx, work, tb);
+    auto kern = precision == 1
+                    ? (S.global_tables ? k_grad_paths<N, true, true> : k_grad_paths<N, true, false>)
+                    : (S.global_tables ? k_grad_paths<N, false, true> : k_grad_paths<N, false, false>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), tb + tile, stream, S.dev(cws), c, P0, pc, z,
+                       gx, work, tb);
     prof_end(stream, label);
     hipLaunchKernelGGL(k_grad_red1, dim3((S.M + 255) / 256, kRedT), dim3(256), 0, stream, work,
                        pc, S.M, kRedT, part);

@@ -20,10 +20,13 @@
 // The CPU oracle runs the same rules with the same constants.
 //
 // Mixed form: the evaluation (exponentials, contraction) and the LU run in FP32; the exponent
-// sums, the state z, s and every decision stay FP64.  Per group, the evaluation runs in FP64 to
-// polish the start point and in the endgame, after an FP32 evaluation failed (until the next
-// accepted point), and for the rest of the path once kMixedFp64Rejects consecutive steps were
-// rejected, so one launch finishes every path.
+// sums, the state z, s and every decision stay FP64; the start point is polished in FP64.  A
+// path whose FP32 evaluation fails or whose step falls below ds_min is parked at its last
+// accepted point (kParked), one that reaches s = 0 is parked for its endgame (kParkedEnd), and
+// the call's second launch, in FP64, finishes the parked paths: first the rest of the tracks,
+// then the (short) endgames, so that long work does not form the launch's tail.  (Switching a
+// group to FP64 inside the FP32 launch makes its whole wave run both precisions, which measured
+// slower.)
 #include <stdio.h>
 
 #include "hom_internal.h"
@@ -35,11 +38,12 @@ constexpr int kTrackBlock = 256;
 enum : int { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
 enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_PREDICT = 2, ACT_END = 3 };
 
-// mixed form: after this many consecutive rejected steps a path evaluates in FP64 for the rest of
-// its track (the FP32 noise floor of the Newton step exceeds tol_track near ill-conditioned
-// points, and halving the step cannot fix that; switching back would only restart the cascade)
-constexpr int kMixedFp64Rejects = 3;
+// statuses of paths parked by the FP32 launch of a mixed call (internal: the call's FP64 launch
+// claims them, so they are never returned)
+constexpr int kParked = 3;     // re-tracked in FP64 from its last accepted point
+constexpr int kParkedEnd = 4;  // at s = 0: only its endgame is left
 
+// LDS of the tracker's lane groups: 4 N complex values per group.
 template <int N>
 __host__ __device__ constexpr size_t track_state_bytes() {
   return (size_t)(kTrackBlock / 64) * Geo<N>::G * 4 * N * sizeof(Cx<double>);
@@ -48,7 +52,7 @@ __host__ __device__ constexpr size_t track_state_bytes() {
 // The tracker loop of one block's lane groups over the paths [p_begin, p_end) of one system.
 // Groups claim paths through `queue` (global memory for a whole launch, or LDS for one work item of
 // the batched form).  Path p's point is z[p * zstride + j], j < n.  slot_state: LDS for the
-// block's groups, 4 N complex values each.
+// block's groups (track_state_bytes).
 template <int N, bool MIXED>
 __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double> *slot_state,
                                             int64_t p_begin, int64_t p_end, int zstride,
@@ -75,9 +79,6 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
   int phase = PH_POLISH, k = 0, steps_here = 0, iters = 0;
   bool need_exact = true;  // next evaluation recomputes the row maximum (fresh path, lost lag)
   double Mlag = 0.0;       // this lane's row maximum from the previous evaluation
-  bool force64 = false;    // mixed form: evaluate in FP64 until the next accepted point
-  int rej_run = 0;         // consecutive rejected steps since the last accepted point
-  bool stay64 = false;     // mixed form: this path evaluates in FP64 from now on
   int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   bool exhausted = !geo.valid;
 #pragma unroll
@@ -91,14 +92,22 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       if (need && r == 0) cl = atomicAdd(queue, 1ull);
       cl = __shfl(cl, geo.base, 64);
       if (need) {
-        if ((int64_t)cl >= P) {
+        // pr.claim: bit 0 fresh paths, bit 1 running ones, bit 2 parked ones (resumed), bit 3
+        // parked endgames.  Endgames are claimed in a second sweep [P, 2P), after every longer
+        // piece of work has started.
+        const int64_t lim = (pr.claim & 8) ? 2 * P : P;
+        if ((int64_t)cl >= lim) {
           exhausted = true;
           need = false;
         } else {
-          const int64_t p = p_begin + (int64_t)cl;
+          const bool second = (int64_t)cl >= P;
+          const int64_t p = p_begin + (second ? (int64_t)cl - P : (int64_t)cl);
           const int st = status[p];
-          const bool fresh = st == 1, resume = st == 2;
-          if (fresh || resume) {
+          const bool fresh = !second && st == 1 && (pr.claim & 1);
+          const bool resume = !second && ((st == 2 && (pr.claim & 2)) ||
+                                          (st == kParked && (pr.claim & 4)));
+          const bool endgame = second && st == kParkedEnd && (pr.claim & 8);
+          if (fresh || resume || endgame) {
             path = p;
             need = false;
 #pragma unroll
@@ -111,14 +120,11 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
             sc = s[p];
             sa = sc;
             ds = fresh ? pr.ds0 : ds_io[p];
-            phase = fresh ? PH_POLISH : PH_RESUME;
+            phase = fresh ? PH_POLISH : (endgame ? PH_END : PH_RESUME);
             k = 0;
             steps_here = 0;
             iters = 0;
             nrm_prev = 0.0;
-            force64 = false;
-            rej_run = 0;
-            stay64 = false;
             need_exact = true;  // also always true with pr.exact_shift
             c0 = counters[4 * p];
             c1 = counters[4 * p + 1];
@@ -132,13 +138,10 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     const bool active = path >= 0;
 
     // ---- one evaluation + consolidated solve (every lane) ----
-    // Mixed form: a group evaluates in FP64 while it polishes its start point and in the
-    // endgame, after an FP32 evaluation failed (until the next accepted point), and for the rest
-    // of the path after kMixedFp64Rejects consecutive rejected steps; otherwise in FP32.  A wave
-    // runs each block only if one of its groups needs it.
+    // Mixed form: a group evaluates in FP64 while it polishes its start point, otherwise in
+    // FP32.  A wave runs each block only if one of its groups needs it.
     bool use64 = true;
-    if constexpr (MIXED)
-      use64 = active && (phase == PH_END || phase == PH_POLISH || force64 || stay64);
+    if constexpr (MIXED) use64 = active && phase == PH_POLISH;
     double nE = 0.0, nN = 0.0, resid = 0.0, ratio = 0.0;
     Cx<double> e = {0.0, 0.0}, q = {0.0, 0.0};
     bool sing = false, shift_ok = true;
@@ -194,7 +197,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     if (!group_shift_ok) continue;  // discard this evaluation; the next one uses exact shifts
 
     // ---- scalar update of the slot (divergent across groups, identical within a group) ----
-    bool fin = false;
+    bool fin = false, park = false;
     int fst = 0;
     if (iters >= pr.max_iters) {
       fin = true;
@@ -211,7 +214,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       const bool nonfin = !(nN <= INFINITY) || !(nE <= INFINITY);
       int act = ACT_NONE;
       if (MIXED && !use64 && (bad_lu || nonfin)) {
-        force64 = true;  // same point again, in FP64 (no state change)
+        park = true;  // re-tracked in FP64 from the last accepted point
+        fst = kParked;
       } else if (bad_lu || nonfin) {
         if (phase == PH_TRACK) {
           act = ACT_REJECT;
@@ -246,12 +250,15 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         sZa[r] = Cx<double>{zo_r, zo_i};
         sEa[r] = e;
         sa = sc;
-        force64 = false;
-        rej_run = 0;
         if (sa >= 0.0) {
-          phase = PH_END;
-          k = 0;
-          act = ACT_END;
+          if (MIXED) {
+            park = true;  // the endgame runs in the FP64 launch
+            fst = kParkedEnd;
+          } else {
+            phase = PH_END;
+            k = 0;
+            act = ACT_END;
+          }
         } else if (steps_here >= pr.max_steps) {
           fin = true;
           fst = 2;  // RUNNING
@@ -286,8 +293,11 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       if (act == ACT_REJECT) {
         ++c1;
         ds *= 0.5;
-        if (MIXED && ++rej_run >= kMixedFp64Rejects) stay64 = true;
-        if (ds < pr.ds_min) {
+        if (MIXED && ds < pr.ds_min) {
+          park = true;  // in FP64, from the last accepted point with a fresh step
+          fst = kParked;
+          ds = pr.ds0;
+        } else if (ds < pr.ds_min) {
           fin = true;
           fst = -2;
           // the reported point is the last accepted one
@@ -351,6 +361,17 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         }
       }
     }
+    if (park) {  // the last accepted point (in PH_RESUME the current point is that point)
+      if (phase == PH_TRACK) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (geo.valid) {
+          zo_r = sZa[r].x;
+          zo_i = sZa[r].y;
+        }
+        sc = sa;
+      }
+      fin = true;
+    }
     if (fin) {
       const int64_t p = path;
       if (r < n) {
@@ -374,14 +395,14 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
 
 // Single system: all P paths, one global work queue.  At most 256 registers per lane, so two
 // waves share each SIMD (the FP64 form at n = 10 needs slightly more without the bound).
-template <int N, bool MIXED>
+template <int N, bool MIXED, bool GT>
 __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_eu(2)))
     k_track(SysDev sd, const double *__restrict__ c, int64_t P, double *__restrict__ z,
             double *__restrict__ s, double *__restrict__ ds_io, int32_t *__restrict__ status,
             int32_t *__restrict__ counters, TrackDev pr, unsigned long long *__restrict__ queue,
             size_t table_bytes, unsigned long long *__restrict__ units) {
   extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N>(smem, sd, c);
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n, z,
                         s, ds_io, status, counters, pr, queue, units);
 }
@@ -395,7 +416,8 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
                           hipStream_t stream) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
   const size_t lds = tb + track_state_bytes<N>();
-  auto kern = mixed ? k_track<N, true> : k_track<N, false>;
+  auto kern = mixed ? (S.global_tables ? k_track<N, true, true> : k_track<N, true, false>)
+                    : (S.global_tables ? k_track<N, false, true> : k_track<N, false, false>);
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTrackBlock, lds);
   if (e != hipSuccess) return e;
@@ -444,7 +466,10 @@ hipError_t launch_track(const System &S, const void *cws, const double *c, int64
 // ------------------------------------------------------------------------------------------
 // Batched form: many systems of uneven n and support sizes in one persistent launch.
 // ------------------------------------------------------------------------------------------
-constexpr size_t kBatchStateBytes = 16 * 1024;  // >= 4 waves x G groups x 4N complex, any N
+constexpr size_t kBatchStateBytes = 16 * 1024;  // >= track_state_bytes<N>() for every N
+static_assert(track_state_bytes<2>() <= kBatchStateBytes && track_state_bytes<3>() <= kBatchStateBytes &&
+                  track_state_bytes<5>() <= kBatchStateBytes && track_state_bytes<7>() <= kBatchStateBytes,
+              "batch LDS state budget");
 
 // One work item: paths [p_begin, p_end) of system b, tracked by the block's lane groups sized
 // for b.N.  The tables go to LDS when they fit the budget, else they are read where they are.
@@ -461,13 +486,18 @@ __device__ __forceinline__ void batch_item(char *smem, const BatchSysDev &b,
                                            unsigned long long *units, size_t table_budget) {
   const SysDev sd{b.n, b.mmax, b.M, T_all + b.T_off, ints_all + b.ints_off,
                   ints_all + b.ints_off + b.n};
-  SysLds<N> S;
-  if (b.lds_bytes > 0)
-    S = stage_tables<N>(smem, sd, c + 2 * b.c_off);  // block-uniform branch (one item per block)
-  else
-    S = SysLds<N>{sd.T, Cg + b.C_off, Cabs_g + b.C_off, sd.mk, b.n, b.mmax};
-  track_slots<N, MIXED>(S, b.n, reinterpret_cast<Cx<double> *>(smem + table_budget), p_begin,
-                        p_end, zstride, z, s, ds, status, counters, pr, lq, units);
+  // block-uniform branch (one item per block); one inlined tracker per table location, so the
+  // staged case reads its tables with LDS instructions
+  Cx<double> *slots = reinterpret_cast<Cx<double> *>(smem + table_budget);
+  if (b.lds_bytes > 0) {
+    const SysLds<N> S = stage_tables<N, false>(smem, sd, c + 2 * b.c_off);
+    track_slots<N, MIXED>(S, b.n, slots, p_begin, p_end, zstride, z, s, ds, status, counters, pr,
+                          lq, units);
+  } else {
+    const SysLds<N> S{sd.T, Cg + b.C_off, Cabs_g + b.C_off, sd.mk, b.n, b.mmax};
+    track_slots<N, MIXED>(S, b.n, slots, p_begin, p_end, zstride, z, s, ds, status, counters, pr,
+                          lq, units);
+  }
 }
 
 template <bool MIXED>

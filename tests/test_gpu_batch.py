@@ -80,3 +80,87 @@ def test_batch_rejects_bad_use(hom):
         hom.track(b, c, z, -32.0)  # no sys_idx
     with pytest.raises(hom.HomError):
         hom.eval(b, c, z[:, :3], np.zeros(len(z)))  # batch handles: track only
+
+
+def _state(hom, torch, z, P):
+    return hom.TrackState(torch.tensor(z, dtype=torch.complex128, device="cuda"),
+                          torch.full((P,), -32.0, dtype=torch.float64, device="cuda"),
+                          torch.zeros(P, dtype=torch.float64, device="cuda"),
+                          torch.full((P,), hom.PATH_START, dtype=torch.int32, device="cuda"),
+                          torch.zeros((P, 4), dtype=torch.int32, device="cuda"))
+
+
+def test_batch_tile_independent(hom):
+    """The work-item size changes only the schedule: FP64 endpoints are bitwise equal for every
+    tile the autotuner may pick."""
+    say("[batch] tiles 1, 2, 8, 16 vs default")
+    systems, starts, z, idx, c = _batch(seed=8, specs=((5, 6, 60), (12, 9, 80), (24, 40, 30)))
+    b = hom.Batch(systems)
+    ref = hom.track(b, c, z, -32.0, hom.default_params(hom.FP64), sys_idx=idx)
+    for t in (1, 2, 8, 16):
+        st = hom.track(b, c, z, -32.0, hom.default_params(hom.FP64, tile=t), sys_idx=idx)
+        assert np.array_equal(_np(st.z), _np(ref.z)), t
+        assert np.array_equal(_np(st.status), _np(ref.status)), t
+
+
+def test_autotune_picks_and_caches(hom, tmp_path):
+    from paper_2111_14317_amd import autotune
+    say("[batch] autotune, 3 systems")
+    systems, starts, z, idx, c = _batch(seed=9, specs=((6, 8, 200), (10, 12, 300), (16, 20, 100)))
+    b = hom.Batch(systems)
+    cache = str(tmp_path / "tiles.json")
+    best, times = autotune.tune(hom, b, c, z, -32.0, idx, hom.MIXED, candidates=(1, 4),
+                                sample_every=2, cache_path=cache)
+    say(f"  times {times} -> tile {best}")
+    assert best in (1, 4) and set(times) == {1, 4} and all(v > 0 for v in times.values())
+    again, times2 = autotune.tune(hom, b, c, z, -32.0, idx, hom.MIXED, candidates=(1, 4),
+                                  sample_every=2, cache_path=cache)
+    assert again == best and times2 == times  # served from the cache
+
+
+def test_batch_graph_replay(hom):
+    """The batched launch captured in a HIP graph: three replays, each after an eager reset of the
+    state (and eager tracking work in between), equal the eager run bitwise (FP64)."""
+    import torch
+    say("[batch] hipGraph capture and replay")
+    systems, starts, z, idx, c = _batch(seed=10, specs=((4, 5, 40), (9, 10, 60), (20, 36, 20)))
+    b = hom.Batch(systems)
+    P = len(z)
+    params = hom.default_params(hom.FP64)
+    ct = torch.tensor(c, dtype=torch.complex128, device="cuda")
+    it = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    z0 = torch.tensor(z, dtype=torch.complex128, device="cuda")
+    eager = hom.track(b, ct, z0, -32.0, params, sys_idx=it)
+    ez, est = _np(eager.z), _np(eager.status)
+    st = _state(hom, torch, z, P)
+
+    def reset():
+        st.z.copy_(z0)
+        st.s.fill_(-32.0)
+        st.ds.zero_()
+        st.status.fill_(hom.PATH_START)
+        st.counters.zero_()
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up launch off the default stream, as capture requires
+        hom.track(b, ct, None, None, params, state=st, sys_idx=it)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    reset()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        hom.track(b, ct, None, None, params, state=st, sys_idx=it)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        reset()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        assert np.array_equal(_np(st.z), ez), rep
+        assert np.array_equal(_np(st.status), est), rep
+        other = hom.track(b, ct, z0, -32.0, params, sys_idx=it)  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(other.z), ez)

@@ -147,3 +147,27 @@ def test_failure_modes_forced(hom):
     assert (_np(st.status) == hom.PATH_RUNNING).all() and (_np(st.s) == -32.0).all()
     st = hom.track(h, csys.c, z0[:0], -32.0)  # P = 0
     assert st.z.shape[0] == 0
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 7, 12, 13, 16, 20, 24, 32])
+def test_every_group_size(hom, n):
+    """One planted system per compiled group size (n = 13 and 16 both run on 16-lane groups;
+    n = 24, 32 read their tables from global memory): both precisions end >= 95% of the paths
+    OK, FP64 endpoints match the oracle's, every OK endpoint is a root."""
+    say(f"[track group size] n={n} P=40")
+    rng = np.random.default_rng(200 + n)
+    sy = W.random_system(n, 10, W._uniform_exps(-3, 3), "unit", 63, rng, rng, rng)
+    csys, cell = W.plant_cell(sy, 63, rng, min_det=40)
+    z0 = W.binomial_start_points(csys, cell, 40, rng)
+    h = hom.System.from_workload(csys)
+    ze, _, _, ost, _ = oracle.track(csys, csys.c, z0[:16], -32.0)
+    for prec in (hom.FP64, hom.MIXED):
+        st = hom.track(h, csys.c, z0, -32.0, hom.default_params(prec))
+        s = _np(st.status)
+        say(f"  prec {prec}: ok {(s == 0).mean():.3f}")
+        assert (s == 0).mean() >= 0.95, np.unique(s, return_counts=True)
+        ok = s == 0
+        assert oracle.residual(csys, csys.c, _np(st.z)[ok]).max() <= 1e-10
+        both = ok[:16] & (ost == 0)
+        tol = 1e-12 if prec == hom.FP64 else 1e-10
+        assert np.quantile(mod2pi_dist(_np(st.z)[:16][both], ze[both]), 0.9) <= tol
