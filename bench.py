@@ -123,15 +123,17 @@ def run_form(hom, torch, h, csys, z0, precision, steps, warmup):
         ok.append(float((st == hom.PATH_OK).float().mean()))
         evals_per_path.append(float(cnt[:, 3].float().mean()))
     sec = t1 - t0
-    kern, units = {}, {}
-    for name, ms, u in prof:
-        kern.setdefault(name, []).append(ms)
-        units.setdefault(name, []).append(u)
+    kern, units = {}, {}  # per step: summed over the launches of one label (the mixed form
+    for name, ms, u in prof:  # runs k_track<n,fp64> twice per step: polish, then finish)
+        kern[name] = kern.get(name, 0.0) + ms / steps
+        units[name] = units.get(name, 0.0) + u / steps
+    launches = {}
+    for name, _, _ in prof:
+        launches[name] = launches.get(name, 0) + 1
     return dict(rate=evals / sec, ms_per_step=1e3 * sec / steps, ok_frac=min(ok),
                 evals_per_path=sum(evals_per_path) / len(evals_per_path),
-                evals_per_step=evals / steps, kernels={k: sum(v) / len(v) for k, v in kern.items()},
-                units={k: sum(v) / len(v) for k, v in units.items()},
-                launches={k: len(v) for k, v in kern.items()}, paths_per_s=P * steps / sec)
+                evals_per_step=evals / steps, kernels=kern, units=units,
+                launches={k: v / steps for k, v in launches.items()}, paths_per_s=P * steps / sec)
 
 
 # dense-support configuration: n = 32, 128 monomials per equation, 262144 points (eval and step)
@@ -252,12 +254,12 @@ def main():
     csys, z0 = _workload(args.paths)
     h = hom.System.from_workload(csys)
     if args.copy_calib:  # known traffic for scaling the HBM counters: write 512 MiB, read 512 MiB
-        buf = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
-        buf.fill_(1)
+        buf = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+        buf.fill_(1.0)  # writes 512 MiB
         torch.cuda.synchronize()
-        total = int(torch.sum(buf, dtype=torch.int64))
+        total = float(torch.sum(buf))  # reads 512 MiB
         torch.cuda.synchronize()
-        assert total == 512 << 20
+        assert total > 0
         del buf
     res = {}
     for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):

@@ -186,11 +186,12 @@ int hom_track_params_default(hom_track_params *p, int precision);
  * sys_idx int32 [P] gives each path's system, non-decreasing (each system's paths contiguous),
  * values in [0, num_sys).  Work items are (system, run of consecutive paths); a block stages the
  * system's tables and its lane groups (sized for that system's n) claim the item's paths.
- * With precision HOM_MIXED the call makes two launches.  The first tracks in FP32 (evaluations
- * and solves; exponent sums, state and decisions in FP64; start points polished in FP64) and
- * parks every path that reaches s = 0, and at its last accepted point every path whose FP32
- * evaluation fails or whose step falls below ds_min (statuses 3 and 4, internal).  The second,
- * in FP64, finishes the parked paths: first the rest of those tracks, then the endgames.
+ * With precision HOM_MIXED the call makes three launches: FP64 polish of the fresh start
+ * points; FP32 tracking (evaluations and solves; exponent sums, state and decisions in FP64),
+ * which parks every path that reaches s = 0, and at its last accepted point every path whose
+ * FP32 evaluation fails, whose step falls below 1e-6 (or ds_min), that has 5 consecutive
+ * rejected steps, that diverges or that has spent max_iters / 8 iterations (statuses 3 and 4,
+ * internal); FP64 for the parked paths, first the rest of those tracks, then the endgames.
  * Resume: calling with max_steps = k until no path is RUNNING gives the same endpoints as one
  * call; bitwise the same z and s with HOM_TRACK_EXACT_SHIFT (the counters then include one extra
  * eval+solve per resume), equal to rounding otherwise (the row shifts differ after a resume).

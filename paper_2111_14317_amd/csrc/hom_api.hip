@@ -569,7 +569,7 @@ static TrackDev to_dev(const hom_track_params *p) {
   return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
                   p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
                   p->max_newton, p->max_end,    p->max_steps, p->max_iters,
-                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3};
+                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3, 0};
 }
 
 int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
@@ -595,18 +595,30 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   hipStream_t st = (hipStream_t)stream;
   const TrackDev pr = to_dev(params);
   const bool mixed = params->precision == HOM_MIXED;
-  // The mixed form runs two launches: FP32 tracking of fresh and running paths (which parks the
-  // paths that need FP64, and every endgame), then FP64 for the parked paths.
-  TrackDev pr64 = pr;
+  // The mixed form runs three launches: FP64 polish of the fresh paths, FP32 tracking of the
+  // running paths (which parks the paths that need FP64, and every endgame), FP64 for the parked
+  // paths.  The FP64 form runs one.
+  TrackDev pr_pol = pr, pr32 = pr, pr64 = pr;
+  pr_pol.claim = 1;
+  pr_pol.polish_only = 1;
+  pr32.claim = 2;
   pr64.claim = 4 | 8;
   hipError_t e = hipSuccess;
   if (batch) {
     // workspace: queue counter, per-system path and item offsets, table-order coefficients
     void *ws = nullptr;
     HOM_HIP(hipMallocAsync(&ws, track_batch_ws_bytes(h->s), st), "hom_track: workspace");
-    e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr, mixed, ws, st);
-    if (e == hipSuccess && mixed)
-      e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr64, false, ws, st);
+    if (!mixed) {
+      e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr, false, ws, st);
+    } else {
+      e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr_pol, false, ws,
+                             st);
+      if (e == hipSuccess)
+        e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr32, true, ws, st);
+      if (e == hipSuccess)
+        e = launch_track_batch(h->s, c, P, z, s, ds, sys_idx, status, counters, pr64, false, ws,
+                               st);
+    }
     hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) HOM_HIP(e, "hom_track");
     HOM_HIP(e2, "hom_track: free workspace");
@@ -617,8 +629,12 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   HOM_HIP(hipMallocAsync((void **)&queue, 256, st), "hom_track: workspace");
   void *cws = nullptr;
   e = coeff_begin(h->s, c, st, &cws);
-  if (e == hipSuccess)
-    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr, mixed, queue, st);
+  if (e == hipSuccess && !mixed)
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr, false, queue, st);
+  if (e == hipSuccess && mixed)
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_pol, false, queue, st);
+  if (e == hipSuccess && mixed)
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr32, true, queue, st);
   if (e == hipSuccess && mixed)
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
   hipError_t e2 = coeff_end(cws, st);

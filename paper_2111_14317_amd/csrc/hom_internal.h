@@ -84,6 +84,7 @@ struct TrackDev {
   int tile;
   int claim;  // statuses a launch takes up: bit 0 fresh (1), bit 1 running (2), bit 2 parked
               // (3), bit 3 parked for the endgame (4)
+  int polish_only;  // fresh paths stop RUNNING once polished (the mixed form's first launch)
 };
 
 

@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 // FP64 engine
 // ------------------------------------------------------------------------------------------
 template <typename OutT>
-__global__ void __launch_bounds__(kDenseBlock)
+__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2)))
     k_dense_f64(DenseDev D, const Cx<double> *__restrict__ Cd, int64_t p0, int64_t p1,
                 const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
                 double *__restrict__ logscale, int flags, unsigned long long *units) {
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(kDenseBlock)
           }
         }
         const f64x4_t dr = dr0 + dr1, di = di0 + di1;
-#pragma unroll
+#pragma unroll 1  // one element at a time: two waves per SIMD fit
         for (int r = 0; r < 4; ++r) {
           const int i = t * 16 + row_f64(q, r);
           const double w = D.W[i];

@@ -19,12 +19,16 @@
 //              step stops contracting; OK when the relative residual <= res_tol.
 // The CPU oracle runs the same rules with the same constants.
 //
-// Mixed form: the evaluation (exponentials, contraction) and the LU run in FP32; the exponent
-// sums, the state z, s and every decision stay FP64; the start point is polished in FP64.  A
-// path whose FP32 evaluation fails or whose step falls below ds_min is parked at its last
-// accepted point (kParked), one that reaches s = 0 is parked for its endgame (kParkedEnd), and
-// the call's second launch, in FP64, finishes the parked paths: first the rest of the tracks,
-// then the (short) endgames, so that long work does not form the launch's tail.  (Switching a
+// Mixed form, three launches.  An FP64 launch polishes the fresh start points (and leaves them
+// RUNNING).  The FP32 launch tracks: the evaluation (exponentials, contraction) and the LU run in
+// FP32; the exponent sums, the state z, s and every decision stay FP64.  A path whose FP32
+// evaluation fails, whose step falls below ds_min, that has kMixedFp64Rejects consecutive rejected
+// steps or that leaves the region |Re z| <= div_re is parked at its last accepted point
+// (kParked: re-tracked in FP64 with a fresh step), one that
+// reaches s = 0 is parked for its endgame (kParkedEnd), and a last FP64
+// launch finishes the parked paths: first the rest of the tracks, then the (short) endgames, so
+// that long work does not form the launch's tail.  The FP32 launch holds no FP64 evaluation
+// code, which keeps its register budget to the FP32 path.  (Switching a
 // group to FP64 inside the FP32 launch makes its whole wave run both precisions, which measured
 // slower.)
 #include <stdio.h>
@@ -38,15 +42,35 @@ constexpr int kTrackBlock = 256;
 enum : int { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
 enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_PREDICT = 2, ACT_END = 3 };
 
+// mixed form: a path with this many consecutive rejected steps is handed to FP64.  Near an
+// ill-conditioned point the FP32 Newton noise exceeds tol_track and halving the step cannot fix
+// that; left in FP32 such a path creeps on with tiny steps until its iteration budget runs out.
+constexpr int kMixedFp64Rejects = 5;
+// ... and so is a path whose step falls below this (steps this small resolve nothing at the FP32
+// Newton tolerance; a path alternating accepted and rejected steps never reaches the reject run)
+constexpr double kMixedMinStep = 1e-6;
 // statuses of paths parked by the FP32 launch of a mixed call (internal: the call's FP64 launch
 // claims them, so they are never returned)
 constexpr int kParked = 3;     // re-tracked in FP64 from its last accepted point
 constexpr int kParkedEnd = 4;  // at s = 0: only its endgame is left
 
-// LDS of the tracker's lane groups: 4 N complex values per group.
+// LDS of the tracker's lane groups: 5 N complex values per group.
 template <int N>
 __host__ __device__ constexpr size_t track_state_bytes() {
-  return (size_t)(kTrackBlock / 64) * Geo<N>::G * 4 * N * sizeof(Cx<double>);
+  return (size_t)(kTrackBlock / 64) * Geo<N>::G * 5 * N * sizeof(Cx<double>);
+}
+
+// The group's current point, read from LDS into registers for one evaluation (so the replicas are
+// dead during the LU, which matters for the register budget at large N).
+template <int N>
+__device__ __forceinline__ void load_point_lds(const Cx<double> *sZc, int n, double (&zr)[N],
+                                               double (&zi)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const Cx<double> v = sZc[j];
+    zr[j] = j < n ? v.x : 0.0;
+    zi[j] = j < n ? v.y : 0.0;
+  }
 }
 
 // The tracker loop of one block's lane groups over the paths [p_begin, p_end) of one system.
@@ -64,25 +88,25 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
                                             unsigned long long *__restrict__ units) {
   const Geo<N> geo;
   const int r = geo.r;
-  // per-group state in LDS: accepted point, Euler direction there, current dE and dN
+  // per-group state in LDS: accepted point, Euler direction there, current dE and dN, current
+  // point (each lane keeps its own coordinate in registers and writes it here)
   const int slot = (threadIdx.x >> 6) * Geo<N>::G + (geo.valid ? geo.g : 0);
-  Cx<double> *sZa = slot_state + slot * 4 * N;
+  Cx<double> *sZa = slot_state + slot * 5 * N;
   Cx<double> *sEa = sZa + N;
   Cx<double> *sEc = sZa + 2 * N;
   Cx<double> *sNc = sZa + 3 * N;
+  Cx<double> *sZc = sZa + 4 * N;
   const int64_t P = p_end - p_begin;
 
-  double zr[N], zi[N];  // the path's point, replicated in every lane of the group
-  double zo_r = 0.0, zo_i = 0.0;  // this lane's own coordinate z_r (same bits as zr[r], zi[r])
+  double zo_r = 0.0, zo_i = 0.0;  // this lane's own coordinate z_r of the current point
   double sc = 0.0, sa = 0.0, ds = 0.0, nrm_prev = 0.0;
   int64_t path = -1;
   int phase = PH_POLISH, k = 0, steps_here = 0, iters = 0;
   bool need_exact = true;  // next evaluation recomputes the row maximum (fresh path, lost lag)
   double Mlag = 0.0;       // this lane's row maximum from the previous evaluation
   int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  int rej_run = 0;  // mixed form: consecutive rejected steps since the last accepted point
   bool exhausted = !geo.valid;
-#pragma unroll
-  for (int j = 0; j < N; ++j) zr[j] = zi[j] = 0.0;
 
   for (;;) {
     // ---- claim paths for idle slots (wave-uniform loop: it shuffles) ----
@@ -110,13 +134,9 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           if (fresh || resume || endgame) {
             path = p;
             need = false;
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-              zr[j] = j < n ? z[2 * (p * zstride + j)] : 0.0;
-              zi[j] = j < n ? z[2 * (p * zstride + j) + 1] : 0.0;
-            }
             zo_r = r < n ? z[2 * (p * zstride + r)] : 0.0;
             zo_i = r < n ? z[2 * (p * zstride + r) + 1] : 0.0;
+            sZc[r] = Cx<double>{zo_r, zo_i};
             sc = s[p];
             sa = sc;
             ds = fresh ? pr.ds0 : ds_io[p];
@@ -126,6 +146,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
             iters = 0;
             nrm_prev = 0.0;
             need_exact = true;  // also always true with pr.exact_shift
+            rej_run = 0;
             c0 = counters[4 * p];
             c1 = counters[4 * p + 1];
             c2 = counters[4 * p + 2];
@@ -138,21 +159,23 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     const bool active = path >= 0;
 
     // ---- one evaluation + consolidated solve (every lane) ----
-    // Mixed form: a group evaluates in FP64 while it polishes its start point, otherwise in
-    // FP32.  A wave runs each block only if one of its groups needs it.
-    bool use64 = true;
-    if constexpr (MIXED) use64 = active && phase == PH_POLISH;
+    // The mixed form's launch evaluates in FP32 only (its paths arrive polished in FP64).
+    constexpr bool use64 = !MIXED;
     double nE = 0.0, nN = 0.0, resid = 0.0, ratio = 0.0;
     Cx<double> e = {0.0, 0.0}, q = {0.0, 0.0};
     bool sing = false, shift_ok = true;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the group's sZc writes
+    __builtin_amdgcn_wave_barrier();
     {
       const double Min = Mlag;
       double M;
       if constexpr (MIXED) {
-        if (__any(!use64)) {
+        {
           Cx<float> row[N + 2], ef, qf;
           float absum, rf;
           double Ml = Min;
+          double zr[N], zi[N];
+          load_point_lds<N>(sZc, n, zr, zi);
           shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
           const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
           sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
@@ -163,28 +186,36 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           Mlag = Ml;
         }
       }
-      if (__any(use64)) {
+      if constexpr (!MIXED) {
         Cx<double> row[N + 2], ed, qd;
         double absum, rd, nEd, nNd, Ml = Min;
+        double zr[N], zi[N];
+        load_point_lds<N>(sZc, n, zr, zi);
         const bool okd = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
         const double h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
         const bool sd = lu_solve2<N, double>(row, r, geo.base, n, ed, qd, nEd, nNd, rd);
         const double resd = group_max<N, double>(h2, r, geo.base);  // squared relative residual
-        if (use64) {
-          e = ed;
-          q = qd;
-          sing = sd;
-          ratio = rd;
-          nE = nEd;
-          nN = nNd;
-          resid = resd;
-          shift_ok = okd;
-          Mlag = Ml;
-        }
+        e = ed;
+        q = qd;
+        sing = sd;
+        ratio = rd;
+        nE = nEd;
+        nN = nNd;
+        resid = resd;
+        shift_ok = okd;
+        Mlag = Ml;
       }
     }
     // every lane of the group must have kept its terms in range, else redo with exact shifts
     const bool group_shift_ok = group_max_u32<N>(shift_ok ? 0u : 1u, r, geo.base) == 0u;
+    // group-wide tests of the Newton update z + dN (computed by every lane, before the branches)
+    const double cre = zo_r + q.x, cim = zo_i + q.y;
+    const bool div_any =
+        group_max_u32<N>((r < n && fabs(cre) > pr.div_re) ? 1u : 0u, r, geo.base) != 0u;
+    double zn2 = 0.0;  // max_j |z_j + dN_j|^2, for the endgame's stopping test (every group that
+    // may run an endgame step in this iteration: in the endgame, or accepting its point at s = 0)
+    if (__any(active && (phase == PH_END || sc >= 0.0)))
+      zn2 = group_max<N, double>(r < n ? cre * cre + cim * cim : 0.0, r, geo.base);
     if (geo.valid) {  // lanes past the last full group own no slot
       sEc[r] = e;
       sNc[r] = q;
@@ -199,7 +230,11 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     // ---- scalar update of the slot (divergent across groups, identical within a group) ----
     bool fin = false, park = false;
     int fst = 0;
-    if (iters >= pr.max_iters) {
+    if (MIXED && iters >= pr.max_iters / 8 && phase == PH_TRACK) {
+      park = true;  // an eighth of the iteration budget spent in FP32: FP64 takes over
+      fst = kParked;
+      ds = pr.ds0;
+    } else if (iters >= pr.max_iters) {
       fin = true;
       fst = -7;
     } else {
@@ -213,9 +248,10 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       const bool bad_lu = sing || !(ratio >= sing_ratio);
       const bool nonfin = !(nN <= INFINITY) || !(nE <= INFINITY);
       int act = ACT_NONE;
-      if (MIXED && !use64 && (bad_lu || nonfin)) {
+      if (MIXED && (bad_lu || nonfin)) {
         park = true;  // re-tracked in FP64 from the last accepted point
         fst = kParked;
+        ds = pr.ds0;
       } else if (bad_lu || nonfin) {
         if (phase == PH_TRACK) {
           act = ACT_REJECT;
@@ -224,17 +260,14 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           fst = bad_lu ? -1 : -4;
         }
       } else if (phase == PH_POLISH) {
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-          if (j < n) {
-            zr[j] += sNc[j].x;
-            zi[j] += sNc[j].y;
-          }
-        zo_r += q.x;
-        zo_i += q.y;
+        zo_r = cre;
+        zo_i = cim;
         ++k;
         ++c2;
-        if (nrm <= tol_polish) {
+        if (nrm <= tol_polish && pr.polish_only) {
+          fin = true;  // polished: the mixed form's FP32 launch resumes it
+          fst = 2;
+        } else if (nrm <= tol_polish) {
           phase = PH_RESUME;
           k = 0;
         } else if (k >= pr.max_polish) {
@@ -250,6 +283,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         sZa[r] = Cx<double>{zo_r, zo_i};
         sEa[r] = e;
         sa = sc;
+        rej_run = 0;
         if (sa >= 0.0) {
           if (MIXED) {
             park = true;  // the endgame runs in the FP64 launch
@@ -269,20 +303,16 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         act = ACT_END;
       } else {  // corrector not converged yet
         if (k < pr.max_newton && (k == 0 || nrm <= 0.5 * nrm_prev)) {
-          bool div = false;
-#pragma unroll
-          for (int j = 0; j < N; ++j)
-            if (j < n) {
-              zr[j] += sNc[j].x;
-              zi[j] += sNc[j].y;
-              div |= fabs(zr[j]) > pr.div_re;
-            }
-          zo_r += q.x;
-          zo_i += q.y;
+          zo_r = cre;
+          zo_i = cim;
           ++k;
           ++c2;
           nrm_prev = nrm;
-          if (div) {
+          if (div_any && MIXED) {
+            park = true;  // re-tracked in FP64 (a tolerance-driven jump can end out here)
+            fst = kParked;
+            ds = pr.ds0;
+          } else if (div_any) {
             fin = true;
             fst = -3;
           }
@@ -293,7 +323,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       if (act == ACT_REJECT) {
         ++c1;
         ds *= 0.5;
-        if (MIXED && ds < pr.ds_min) {
+        if (MIXED && (++rej_run >= kMixedFp64Rejects || ds < kMixedMinStep || ds < pr.ds_min)) {
           park = true;  // in FP64, from the last accepted point with a fresh step
           fst = kParked;
           ds = pr.ds0;
@@ -302,12 +332,6 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           fst = -2;
           // the reported point is the last accepted one
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-#pragma unroll
-          for (int j = 0; j < N; ++j)
-            if (j < n) {
-              zr[j] = sZa[j].x;
-              zi[j] = sZa[j].y;
-            }
           if (geo.valid) {
             zo_r = sZa[r].x;
             zo_i = sZa[r].y;
@@ -320,13 +344,6 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       if (act == ACT_PREDICT) {
         const double hstep = fmin(ds, -sa);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-          if (j < n) {
-            const Cx<double> za = sZa[j], ea = sEa[j];
-            zr[j] = fma(hstep, ea.x, za.x);
-            zi[j] = fma(hstep, ea.y, za.y);
-          }
         if (geo.valid) {
           const Cx<double> za = sZa[r], ea = sEa[r];
           zo_r = fma(hstep, ea.x, za.x);
@@ -338,18 +355,9 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       }
       if (act == ACT_END) {
         {
-          double zn2 = 0.0;
-#pragma unroll
-          for (int j = 0; j < N; ++j)
-            if (j < n) {
-              zr[j] += sNc[j].x;
-              zi[j] += sNc[j].y;
-              const double a = zr[j] * zr[j] + zi[j] * zi[j];
-              zn2 = (a > zn2 || a != a) ? a : zn2;
-            }
           const double zn = sqrt(zn2);
-          zo_r += q.x;
-          zo_i += q.y;
+          zo_r = cre;
+          zo_i = cim;
           ++c2;
           ++k;
           if (nrm <= pr.tol_end * (1.0 + zn) || k >= pr.max_end || (k >= 3 && nrm > 0.5 * nrm_prev)) {
@@ -361,6 +369,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         }
       }
     }
+    if (geo.valid) sZc[r] = Cx<double>{zo_r, zo_i};  // read by the group's next evaluation
     if (park) {  // the last accepted point (in PH_RESUME the current point is that point)
       if (phase == PH_TRACK) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -466,7 +475,7 @@ hipError_t launch_track(const System &S, const void *cws, const double *c, int64
 // ------------------------------------------------------------------------------------------
 // Batched form: many systems of uneven n and support sizes in one persistent launch.
 // ------------------------------------------------------------------------------------------
-constexpr size_t kBatchStateBytes = 16 * 1024;  // >= track_state_bytes<N>() for every N
+constexpr size_t kBatchStateBytes = 20 * 1024;  // >= track_state_bytes<N>() for every N
 static_assert(track_state_bytes<2>() <= kBatchStateBytes && track_state_bytes<3>() <= kBatchStateBytes &&
                   track_state_bytes<5>() <= kBatchStateBytes && track_state_bytes<7>() <= kBatchStateBytes,
               "batch LDS state budget");
