@@ -152,6 +152,7 @@ C3_MFMA_BF16 = C3_MONO * ((1 + 6) * 16384 / 256 + 6 * 2 * 16384 / 512)
 #         A3 (K = 4 monomials at a time, two column tiles, Re/Im)
 C3_MFMA_F64 = C3_MONO * ((8 + 8) * 2048 / 256 + 16 * 2048 / 256)
 PEAK_BF16 = 2.5e15
+PEAK_HBM = 8.0e12
 
 
 def run_dense(hom, torch, P, reps=3):
@@ -206,6 +207,48 @@ def run_dense(hom, torch, P, reps=3):
             rec["frac_of_fp64_peak_algorithmic"] = P * C3_FLOPS_EVAL / (ems * 1e-3) / PEAK_FP64
         out[name] = rec
         print(f"# c3 {name}: {ms:.2f} ms, {rec['points_per_s']:.3e} points/s, kernels {kern}",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def run_eval_n10(hom, torch, P=65536, reps=5):
+    """hom_eval and hom_step on P random points of the n = 10 system.  The evaluation reads z, s and
+    writes G and the row scales (2168 B per point at n = 10): it is judged against HBM bandwidth."""
+    import workloads as W
+    sys_, z, s = W.config_system("c2", P=P)
+    n = sys_.n
+    dev = "cuda"
+    c = torch.tensor(sys_.c, dtype=torch.complex128, device=dev)
+    zt = torch.tensor(z, dtype=torch.complex128, device=dev)
+    st = torch.tensor(s, dtype=torch.float64, device=dev)
+    h = hom.System.from_workload(sys_)
+    # bytes per point: z, s in; G, logscale out (eval) / dE, dN, status out (step)
+    b_eval = 16 * n + 8 + 16 * n * (n + 2) + 8 * n
+    b_step = 16 * n + 8 + 2 * 16 * n + 4
+    out = {}
+    for name, kind, arg, nbytes in (("eval_fp64", "eval", 0, b_eval),
+                                    ("eval_fp32", "eval", hom.EVAL_FP32, b_eval),
+                                    ("step_fp64", "step", hom.FP64, b_step),
+                                    ("step_mixed", "step", hom.MIXED, b_step)):
+        def once():
+            if kind == "eval":
+                return hom.eval(h, c, zt, st, flags=arg)
+            return hom.step(h, c, zt, st, precision=arg)
+        once()
+        torch.cuda.synchronize()
+        hom.profile_read()
+        hom.set_profiling(True)
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        hom.set_profiling(False)
+        ms = sum(t for _, t, _ in hom.profile_read()) / reps
+        out[name] = {"ms": ms, "points_per_s": P / (ms * 1e-3), "bytes_per_point": nbytes,
+                     "hbm_gb_per_s": P * nbytes / (ms * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": P * nbytes / (ms * 1e-3) / PEAK_HBM,
+                     "frac_of_fp64_peak": P * (FLOPS_PER_UNIT - (4190 if kind == "eval" else 0))
+                     / (ms * 1e-3) / PEAK_FP64}
+        print(f"# n10 {name} P={P}: {ms:.3f} ms, {out[name]['hbm_gb_per_s']:.0f} GB/s",
               file=sys.stderr, flush=True)
     return out
 
@@ -301,6 +344,8 @@ def main():
         "roofline": roof,
     }
     if not args.no_dense:
+        out["eval_step_n10_65536_points"] = run_eval_n10(hom, torch, P=65536)
+        out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)
         out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(csys, z0)
