@@ -48,6 +48,15 @@ __device__ __forceinline__ Cx<T> cfnms(Cx<T> a, Cx<T> l, Cx<T> b) {
   return r;
 }
 
+// a + l * b
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(Cx<T> a, Cx<T> l, Cx<T> b) {
+  Cx<T> r;
+  r.x = fma(l.x, b.x, fma(-l.y, b.y, a.x));
+  r.y = fma(l.x, b.y, fma(l.y, b.x, a.y));
+  return r;
+}
+
 // 1/x: hardware reciprocal estimate refined by Newton steps (two in FP64: ~1 ulp), instead of the
 // IEEE division sequence.
 __device__ __forceinline__ double fast_rcp(double x) {
@@ -120,6 +129,25 @@ __device__ __forceinline__ T group_max(T v, int r, int base) {
     t = t >= N ? t - N : t;
     const T o = __shfl(v, base + t, 64);
     v = (o > v || o != o) ? o : v;  // propagates NaN
+  }
+  return v;
+}
+
+// Maximum over the group of a value that is >= +0 or NaN: an unsigned maximum of the bit
+// patterns, which is monotone on non-negative floats and puts every NaN above +inf.
+template <int N>
+__device__ __forceinline__ float group_max_nonneg(float v, int r, int base) {
+  return __uint_as_float(group_max_u32<N>(__float_as_uint(v), r, base));
+}
+
+// Bitwise OR over the group (every lane ends with it).
+template <int N>
+__device__ __forceinline__ uint32_t group_or_u32(uint32_t v, int r, int base) {
+#pragma unroll
+  for (int off = 1; off < N; off <<= 1) {
+    int t = r + off;
+    t = t >= N ? t - N : t;
+    v |= (uint32_t)__shfl((int)v, base + t, 64);
   }
   return v;
 }
@@ -302,12 +330,17 @@ __device__ __forceinline__ void eval_row_exact(const SysLds<N> &S, int r, const 
 // max-modulus norms of dE and dN over the true unknowns (identical in every lane; NaN
 // propagates), ratio = min|pivot| / max|pivot| over the true columns.  Returns true when a
 // pivot is zero or not finite.  Every lane of the wave must call this (it shuffles).
+//
+// Elimination: column j's pivot row is found with a packed-key max over the rows not used yet,
+// broadcast entry by entry, and every other unused row subtracts its multiple of it.  Such a row
+// also clears its own entry j (it is zero in exact arithmetic), so in the back substitution every
+// row can apply x_j without a mask: rows pivoted after column j hold zeros there, and the rows
+// that consume x_j are exactly the ones pivoted before it.
 template <int N, typename T>
 __device__ __forceinline__ bool lu_solve2(Cx<T> (&row)[N + 2], int r, int base, int n, Cx<T> &myE,
                                           Cx<T> &myN, double &nrmE, double &nrmN, T &ratio) {
   bool used = false;
-  int my_order = N;
-  Cx<T> inv_mine = {T(0), T(0)};
+  Cx<T> ninv_mine = {T(0), T(0)};  // minus the inverse of this row's pivot
   int pl[N];
   T pmin2 = T(INFINITY), pmax2 = T(0);
   bool sing = false;
@@ -323,50 +356,59 @@ __device__ __forceinline__ bool lu_solve2(Cx<T> (&row)[N + 2], int r, int base, 
     const T mag = pv.x * pv.x + pv.y * pv.y;
     sing |= !(mag > T(0) && mag < T(INFINITY));
     if (j < n) {
-      pmin2 = fmin(pmin2, mag);
-      pmax2 = fmax(pmax2, mag);
+      if constexpr (sizeof(T) == 4) {  // non-negative (NaN is caught by `sing`): integer order
+        pmin2 = __uint_as_float(min(__float_as_uint(pmin2), __float_as_uint(mag)));
+        pmax2 = __uint_as_float(max(__float_as_uint(pmax2), __float_as_uint(mag)));
+      } else {
+        pmin2 = fmin(pmin2, mag);
+        pmax2 = fmax(pmax2, mag);
+      }
     }
-    const T id = fast_rcp(mag);
-    const Cx<T> inv = {pv.x * id, -pv.y * id};
+    const T nid = -fast_rcp(mag);
+    const Cx<T> ninv = {pv.x * nid, -(pv.y * nid)};  // -1 / pivot
     const bool me = (r == idx);
-    Cx<T> l = {T(0), T(0)};
-    if (!used && !me) l = cmul(row[j], inv);
+    const bool elim = !used && !me;
+    Cx<T> l = {T(0), T(0)};  // minus the multiplier
+    if (elim) {
+      l = cmul(row[j], ninv);
+      row[j] = {T(0), T(0)};
+    }
     if (me) {
       used = true;
-      my_order = j;
-      inv_mine = inv;
+      ninv_mine = ninv;
     }
 #pragma unroll
     for (int col = j + 1; col < N + 2; ++col) {
       const Cx<T> pc = shfl_cx(row[col], src);
-      row[col] = cfnms(row[col], l, pc);
+      row[col] = cfma(row[col], l, pc);
     }
   }
-  double nE = 0.0, nN = 0.0;
+  // back substitution, column oriented: at step j the pivot row of column j has its final
+  // right-hand sides and broadcasts the two unknowns, negated (which is what dE and dN hold)
   myE = {T(0), T(0)};
   myN = {T(0), T(0)};
 #pragma unroll
   for (int j = N - 1; j >= 0; --j) {
     const int src = base + pl[j];
-    const Cx<T> e = cmul(row[N], inv_mine), q = cmul(row[N + 1], inv_mine);
+    const Cx<T> e = cmul(row[N], ninv_mine), q = cmul(row[N + 1], ninv_mine);
     const Cx<T> xe = shfl_cx(e, src), xq = shfl_cx(q, src);
-    if (my_order < j) {
-      row[N] = cfnms(row[N], row[j], xe);
-      row[N + 1] = cfnms(row[N + 1], row[j], xq);
-    }
-    if (j < n) {  // squared moduli; one square root at the end (sqrt is monotone)
-      const double ae = (double)xe.x * xe.x + (double)xe.y * xe.y;
-      const double aq = (double)xq.x * xq.x + (double)xq.y * xq.y;
-      nE = (ae > nE || ae != ae) ? ae : nE;
-      nN = (aq > nN || aq != aq) ? aq : nN;
-    }
+    row[N] = cfma(row[N], row[j], xe);
+    row[N + 1] = cfma(row[N + 1], row[j], xq);
     if (r == j) {
-      myE = {-xe.x, -xe.y};
-      myN = {-xq.x, -xq.y};
+      myE = xe;
+      myN = xq;
     }
   }
-  nrmE = sqrt(nE);
-  nrmN = sqrt(nN);
+  // norms over the true unknowns: squared moduli, a group maximum, one square root
+  const T ae = r < n ? myE.x * myE.x + myE.y * myE.y : T(0);
+  const T aq = r < n ? myN.x * myN.x + myN.y * myN.y : T(0);
+  if constexpr (sizeof(T) == 8) {
+    nrmE = sqrt(group_max<N, double>(ae, r, base));
+    nrmN = sqrt(group_max<N, double>(aq, r, base));
+  } else {
+    nrmE = (double)sqrtf(group_max_nonneg<N>(ae, r, base));
+    nrmN = (double)sqrtf(group_max_nonneg<N>(aq, r, base));
+  }
   ratio = sqrt(pmin2 / pmax2);
   return sing;
 }

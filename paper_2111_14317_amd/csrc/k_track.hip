@@ -179,7 +179,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
           const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
           sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
-          resid = group_max<N, double>((double)h2, r, geo.base);
+          resid = group_max_nonneg<N>(h2, r, geo.base);
           e = {ef.x, ef.y};
           q = {qf.x, qf.y};
           ratio = rf;
@@ -206,15 +206,17 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         Mlag = Ml;
       }
     }
-    // every lane of the group must have kept its terms in range, else redo with exact shifts
-    const bool group_shift_ok = group_max_u32<N>(shift_ok ? 0u : 1u, r, geo.base) == 0u;
-    // group-wide tests of the Newton update z + dN (computed by every lane, before the branches)
+    // group-wide flags in one reduction: every lane of the group must have kept its terms in
+    // range (else redo with exact shifts), and the Newton update z + dN must stay in the region
     const double cre = zo_r + q.x, cim = zo_i + q.y;
-    const bool div_any =
-        group_max_u32<N>((r < n && fabs(cre) > pr.div_re) ? 1u : 0u, r, geo.base) != 0u;
+    const uint32_t flags = group_or_u32<N>((shift_ok ? 0u : 1u) |
+                                           ((r < n && fabs(cre) > pr.div_re) ? 2u : 0u), r, geo.base);
+    const bool group_shift_ok = (flags & 1u) == 0u;
+    const bool div_any = (flags & 2u) != 0u;
     double zn2 = 0.0;  // max_j |z_j + dN_j|^2, for the endgame's stopping test (every group that
-    // may run an endgame step in this iteration: in the endgame, or accepting its point at s = 0)
-    if (__any(active && (phase == PH_END || sc >= 0.0)))
+    // may run an endgame step in this iteration: in the endgame, or accepting its point at s = 0;
+    // the mixed form's FP32 launch parks its endgames instead)
+    if (!MIXED && __any(active && (phase == PH_END || sc >= 0.0)))
       zn2 = group_max<N, double>(r < n ? cre * cre + cim * cim : 0.0, r, geo.base);
     if (geo.valid) {  // lanes past the last full group own no slot
       sEc[r] = e;
