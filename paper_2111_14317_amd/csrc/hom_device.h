@@ -70,6 +70,72 @@ __device__ __forceinline__ float fast_rcp(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// ------------------------------------------------------------------------------------------
+// FP64 exponential and sine/cosine of the evaluation's terms (A2)
+// ------------------------------------------------------------------------------------------
+// The library routines accept every input (infinities, huge arguments, denormal results) at
+// several times the cost.  The terms' arguments are bounded: the shifted exponent Re u - M (at
+// most the lag margin above 0; below about -745 the term underflows to 0) and a phase already
+// reduced to [-1/2, 1/2] turns.  On those ranges both functions are accurate to a few ulp; a
+// non-finite argument gives NaN.
+//
+// e^x: Cody-Waite reduction x = k ln 2 + r, |r| <= ln 2 / 2, with ln 2 split into a head whose
+// low 21 bits are zero (k * head is exact for |k| < 2^21) and a tail; the Taylor polynomial of
+// e^r to degree 13 (truncation error below 2^-57 relative); the result scaled by 2^k.
+// sin and cos of 2 pi t for |t| <= 1/2: quadrant q = rint(4 t), f = t - q/4 (exact), the angle
+// 2 pi f in [-pi/4, pi/4] through the Taylor polynomials of sin (degree 17) and cos (degree 16),
+// whose truncation errors stay below 2^-53 there, then the rotation by q quarter turns.
+//
+// The coefficients sit in one compile-time table: 1/k! for e^r (k = 13 down to 0), the sine's
+// (odd k = 17 down to 1, alternating signs), the cosine's (even k = 16 down to 0), then ln 2
+// (head, tail) and 2 pi.
+enum : int { kCoefExp = 0, kCoefSin = 14, kCoefCos = 23, kCoefLn2Hi = 32, kCoefLn2Lo = 33,
+             kCoefTwoPi = 34, kCoefCount = 35 };
+#define HOM_FP64_COEFFICIENTS                                                                     \
+  1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0, 1.0 / 362880.0,      \
+      1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0, \
+      1.0 / 355687428096000.0, -1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0,     \
+      1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0, 1.0,                                \
+      1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0, -1.0 / 3628800.0,          \
+      1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5, 1.0,                                         \
+      0.6931471803691238 /* ln 2, low 21 bits cleared */,                                         \
+      1.9082149292705877e-10 /* ln 2 minus the head */, 6.283185307179586
+struct CoefConst {
+  __host__ __device__ constexpr double operator()(int k) const {
+    constexpr double c[kCoefCount] = {HOM_FP64_COEFFICIENTS};
+    return c[k];
+  }
+};
+__host__ __device__ __forceinline__ double exp_eval(double x) {
+  constexpr CoefConst c{};
+  const double k = rint(x * kLog2e);
+  double r = fma(-k, c(kCoefLn2Hi), x);
+  r = fma(-k, c(kCoefLn2Lo), r);
+  double p = c(kCoefExp);
+#pragma unroll
+  for (int i = 1; i < 14; ++i) p = fma(p, r, c(kCoefExp + i));
+  return ldexp(p, (int)k);
+}
+
+__host__ __device__ __forceinline__ void sincos_turns(double t, double &sn, double &cs) {
+  constexpr CoefConst c{};
+  const double q = rint(4.0 * t);
+  const double th = fma(-0.25, q, t) * c(kCoefTwoPi);
+  const double t2 = th * th;
+  double ps = c(kCoefSin);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) ps = fma(ps, t2, c(kCoefSin + i));
+  const double s0 = th * ps;
+  double pc = c(kCoefCos);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) pc = fma(pc, t2, c(kCoefCos + i));
+  const double c0 = pc;
+  const int qi = (int)q & 3;  // the angle is 2 pi f + qi pi/2
+  const double a = (qi & 1) ? c0 : s0, b = (qi & 1) ? s0 : c0;
+  sn = (qi & 2) ? -a : a;
+  cs = ((qi + 1) & 2) ? -b : b;
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> shfl_cx(Cx<T> v, int src) {
   return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
@@ -280,9 +346,9 @@ __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double
     Cx<T> v;
     T mag;
     if constexpr (sizeof(T) == 8) {
-      mag = exp(re - M);
+      mag = exp_eval(re - M);
       double sn, cs;
-      sincospi(2.0 * turns, &sn, &cs);
+      sincos_turns(turns, sn, cs);
       v.x = mag * (cc.x * cs - cc.y * sn);
       v.y = mag * (cc.x * sn + cc.y * cs);
       absum += mag * S.Cabs[i * n + r];

@@ -10,7 +10,7 @@
 //
 // Two engines:
 //   FP64    16x16x4 f64 MFMA; phase in turns (z's imaginary parts divided by 2 pi and reduced
-//           before the product), exp and sincospi in FP64.
+//           before the product), exponential and sine/cosine in FP64.
 //   BF16x3  16x16x32 bf16 MFMA with FP32 accumulation.  Re z is split into three bf16 parts
 //           (hi + mid + lo, one accumulator); Im z / 2 pi is written as three signed base-512
 //           digits, each product summed in its own accumulator, so the phase is formed exactly
@@ -381,10 +381,10 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
         for (int r = 0; r < 4; ++r) {
           const int i = t * 16 + row_f64(q, r);
           const double w = D.W[i];
-          const double mag = exp(fma(w, sp, dr[r] - Mk));
+          const double mag = exp_eval(fma(w, sp, dr[r] - Mk));
           const double ph = di[r] - rint(di[r]);
           double sn, cs;
-          sincospi(2.0 * ph, &sn, &cs);
+          sincos_turns(ph, sn, cs);
           const Cx<double> cc = Cd[i];
           const double cr = cc.x * mag, ci = cc.y * mag;
           const double vr = cr * cs - ci * sn, vi = cr * sn + ci * cs;

@@ -94,9 +94,9 @@ __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__re
       const float tf = (float)turns;
       E = {(double)(mag * __builtin_amdgcn_cosf(tf)), -(double)(mag * __builtin_amdgcn_sinf(tf))};
     } else {
-      const double mag = exp(re - Mr);
+      const double mag = exp_eval(re - Mr);
       double sn, cs;
-      sincospi(2.0 * turns, &sn, &cs);
+      sincos_turns(turns, sn, cs);
       E = {mag * cs, -mag * sn};
     }
     Cx<double> v = ok ? cmul(Cx<double>{(double)mu.x, (double)mu.y}, E) : Cx<double>{0.0, 0.0};

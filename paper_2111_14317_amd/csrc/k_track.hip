@@ -21,16 +21,19 @@
 //
 // Mixed form, three launches.  An FP64 launch polishes the fresh start points (and leaves them
 // RUNNING).  The FP32 launch tracks: the evaluation (exponentials, contraction) and the LU run in
-// FP32; the exponent sums, the state z, s and every decision stay FP64.  A path whose FP32
-// evaluation fails, whose step falls below ds_min, that has kMixedFp64Rejects consecutive rejected
-// steps or that leaves the region |Re z| <= div_re is parked at its last accepted point
-// (kParked: re-tracked in FP64 with a fresh step), one that
-// reaches s = 0 is parked for its endgame (kParkedEnd), and a last FP64
-// launch finishes the parked paths: first the rest of the tracks, then the (short) endgames, so
-// that long work does not form the launch's tail.  The FP32 launch holds no FP64 evaluation
-// code, which keeps its register budget to the FP32 path.  (Switching a
-// group to FP64 inside the FP32 launch makes its whole wave run both precisions, which measured
-// slower.)
+// FP32; the exponent sums, the state z, s and every decision stay FP64.  A failed FP32 evaluation
+// at a predicted or corrected point (pivots below FP32's reach, non-finite values), or a
+// correction that leaves the region |Re z| <= div_re, rejects the step like any failed
+// correction.  A path whose FP32 evaluation fails at its accepted point, whose step falls below
+// kMixedMinStep or that has kMixedFp64Rejects consecutive rejected steps is parked at its last
+// accepted point (kParked: re-tracked in FP64 with a fresh step); one that reaches s = 0 is
+// parked for its endgame (kParkedEnd).  A last FP64 launch finishes the parked paths: first the
+// rest of the tracks, then the (short) endgames, so that long work does not form the launch's
+// tail.  The FP32 launch holds no FP64 evaluation code, which keeps its register budget to the
+// FP32 path: switching a group to FP64 inside the FP32 launch makes its whole wave run both
+// precisions, and even an FP64 residual pass for the few paths that need it (FP32 LU, FP64
+// residual) slowed the whole launch by a third through its register and code layout, both
+// measured.
 #include <stdio.h>
 
 #include "hom_internal.h"
@@ -45,7 +48,7 @@ enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_PREDICT = 2, ACT_END = 3 };
 // mixed form: a path with this many consecutive rejected steps is handed to FP64.  Near an
 // ill-conditioned point the FP32 Newton noise exceeds tol_track and halving the step cannot fix
 // that; left in FP32 such a path creeps on with tiny steps until its iteration budget runs out.
-constexpr int kMixedFp64Rejects = 5;
+constexpr int kMixedFp64Rejects = 10;
 // ... and so is a path whose step falls below this (steps this small resolve nothing at the FP32
 // Newton tolerance; a path alternating accepted and rejected steps never reaches the reject run)
 constexpr double kMixedMinStep = 1e-6;
@@ -250,11 +253,11 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       const bool bad_lu = sing || !(ratio >= sing_ratio);
       const bool nonfin = !(nN <= INFINITY) || !(nE <= INFINITY);
       int act = ACT_NONE;
-      if (MIXED && (bad_lu || nonfin)) {
-        park = true;  // re-tracked in FP64 from the last accepted point
+      if (MIXED && (bad_lu || nonfin) && phase != PH_TRACK) {
+        park = true;  // the accepted point itself: re-tracked in FP64 from there
         fst = kParked;
         ds = pr.ds0;
-      } else if (bad_lu || nonfin) {
+      } else if (bad_lu || nonfin) {  // a predicted or corrected point: a rejected step
         if (phase == PH_TRACK) {
           act = ACT_REJECT;
         } else {
@@ -311,9 +314,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           ++c2;
           nrm_prev = nrm;
           if (div_any && MIXED) {
-            park = true;  // re-tracked in FP64 (a tolerance-driven jump can end out here)
-            fst = kParked;
-            ds = pr.ds0;
+            act = ACT_REJECT;  // a jump out of the region (FP32 noise can cause it): a shorter step
           } else if (div_any) {
             fin = true;
             fst = -3;
