@@ -27,56 +27,113 @@ __device__ __forceinline__ void load_point(const double *__restrict__ z, int64_t
   }
 }
 
+// Per-wave LDS of k_eval: the wave's points (one complex per lane: lane r of group g holds z_r of
+// the group's point) and a staging buffer through which the rows leave in contiguous 1 KiB
+// stores.  A wave's output rows are consecutive in G ([P][n][n+2]), so the buffer takes them
+// in chunks of whole rows and the wave writes each chunk with 16 bytes per lane.
+constexpr int kEvalStageBytes = 4096;
+constexpr int kEvalWaveBytes = 64 * 16 + kEvalStageBytes;
+
+// FP32 up to 12 lanes per group: three waves per SIMD (at most 168 registers); the others need
+// more and run two.
 template <int N, typename T, bool GT>
-__global__ void __launch_bounds__(kBlock) k_eval(SysDev sd, const double *__restrict__ c,
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && N <= 12 ? 3 : 1)))
+    k_eval(SysDev sd, const double *__restrict__ c,
                                                  int64_t P, const double *__restrict__ z,
                                                  const double *__restrict__ s,
                                                  double *__restrict__ G,
-                                                 double *__restrict__ logscale, int flags) {
+                                                 double *__restrict__ logscale, int flags,
+                                                 size_t table_bytes) {
   extern __shared__ __align__(16) char smem[];
   const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   const Geo<N> geo;
-  if (!geo.valid) return;
-  const int n = sd.n, r = geo.r;
+  const int n = sd.n, r = geo.r, lane = geo.lane;
+  char *wbuf = smem + table_bytes + (threadIdx.x >> 6) * kEvalWaveBytes;
+  Cx<double> *sZ = reinterpret_cast<Cx<double> *>(wbuf);
+  char *stage = wbuf + 64 * 16;
   const int64_t gpb = (kBlock / 64) * Geo<N>::G;
   const int64_t stride = (int64_t)gridDim.x * gpb;
-  for (int64_t p = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g; p < P;
-       p += stride) {
+  const int row_bytes = (n + 2) * 16;
+  const int rows_per_chunk = kEvalStageBytes / row_bytes;
+  // this lane's coordinate of its group's next point, loaded one iteration ahead
+  auto fetch = [&](int64_t q, Cx<double> &zq, double &sq) {
+    const bool ok = geo.valid && q < P;
+    zq = (ok && r < n) ? reinterpret_cast<const Cx<double> *>(z)[q * n + r] : Cx<double>{0.0, 0.0};
+    sq = ok ? s[q] : 0.0;
+  };
+  const int64_t wave0 = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G;
+  Cx<double> zmine;
+  double smine;
+  fetch(wave0 + geo.g, zmine, smine);
+  for (int64_t base = wave0; base < P; base += stride) {  // wave-uniform
+    const int64_t p = base + geo.g;
+    const bool act = geo.valid && p < P;
+    if (geo.valid) sZ[lane] = zmine;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     double zr[N], zi[N];
-    load_point<N>(z, p, n, zr, zi);
-    const double sp = s[p];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const Cx<double> v = geo.valid ? sZ[geo.base + j] : Cx<double>{0.0, 0.0};
+      zr[j] = j < n ? v.x : 0.0;
+      zi[j] = j < n ? v.y : 0.0;
+    }
+    const double sp = smine;
+    fetch(p + stride, zmine, smine);
     Cx<T> row[N + 2];
     double M;
     T absum;
     eval_row_exact<N, T>(S, r, zr, zi, sp, row, M, absum);
-    if (r >= n) continue;
     const double scale = (flags & 1) ? exp(M) : 1.0;  // HOM_UNSCALED
-    double *Gr = G + 2 * ((p * n + r) * (n + 2));
+    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // HOM_AFFINE: H_t = e^{-s} H_s
+    // rows of this wave's block in chunks through the staging buffer
+    const int64_t left = P - base;
+    const int groups = left < Geo<N>::G ? (int)left : Geo<N>::G;
+    const int rows = groups * n;
+    const int q = geo.g * n + r;  // this lane's row within the block
+    const bool owner = act && r < n;
+    double *Gw = G + 2 * (base * n) * (n + 2);
+    for (int c0 = 0; c0 < rows; c0 += rows_per_chunk) {
+      if (owner && q >= c0 && q < c0 + rows_per_chunk) {
+        Cx<double> *dst = reinterpret_cast<Cx<double> *>(stage + (q - c0) * row_bytes);
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      if (j < n) {
-        Cx<double> v = {(double)row[j].x * scale, (double)row[j].y * scale};
-        Gr[2 * j] = v.x;
-        Gr[2 * j + 1] = v.y;
+        for (int j = 0; j < N; ++j)
+          if (j < n) dst[j] = Cx<double>{(double)row[j].x * scale, (double)row[j].y * scale};
+        dst[n] = Cx<double>{(double)row[N].x * fs, (double)row[N].y * fs};
+        dst[n + 1] = Cx<double>{(double)row[N + 1].x * scale, (double)row[N + 1].y * scale};
       }
-    }
-    if (flags & 2) {  // HOM_AFFINE: J_x = J_z diag(e^{-z}), in a loop of its own
-      for (int j = 0; j < n; ++j) {
-        double zre = z[2 * (p * n + j)], zim = z[2 * (p * n + j) + 1];
-        double sn, cs;
-        sincos(-zim, &sn, &cs);
-        const double mag = exp(-zre);
-        const Cx<double> v = cmul(Cx<double>{Gr[2 * j], Gr[2 * j + 1]}, Cx<double>{mag * cs, mag * sn});
-        Gr[2 * j] = v.x;
-        Gr[2 * j + 1] = v.y;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const int nrow = rows - c0 < rows_per_chunk ? rows - c0 : rows_per_chunk;
+      const int pieces = nrow * (n + 2);  // 16-byte pieces of this chunk
+      const double2 *src = reinterpret_cast<const double2 *>(stage);
+      double2 *out = reinterpret_cast<double2 *>(Gw + 2 * (int64_t)c0 * (n + 2));
+      if (flags & 2) {  // HOM_AFFINE: J_x = J_z diag(e^{-z}), on the way out
+        for (int k = lane; k < pieces; k += 64) {
+          const int rq = c0 + k / (n + 2), j = k - (k / (n + 2)) * (n + 2);
+          double2 v = src[k];
+          if (j < n) {
+            const Cx<double> zj = sZ[(rq / n) * N + j];
+            double sn, cs;
+            sincos(-zj.y, &sn, &cs);
+            const double mag = exp(-zj.x);
+            const Cx<double> w = cmul(Cx<double>{v.x, v.y}, Cx<double>{mag * cs, mag * sn});
+            v.x = w.x;
+            v.y = w.y;
+          }
+          out[k] = v;
+        }
+      } else {
+        for (int k = lane; k < pieces; k += 64) out[k] = src[k];
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();  // the buffer is read before the next chunk overwrites it
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // H_t = e^{-s} H_s
-    Gr[2 * n] = (double)row[N].x * fs;
-    Gr[2 * n + 1] = (double)row[N].y * fs;
-    Gr[2 * n + 2] = (double)row[N + 1].x * scale;
-    Gr[2 * n + 3] = (double)row[N + 1].y * scale;
-    if (logscale) logscale[p * n + r] = (flags & 1) ? 0.0 : M;
+    if (logscale && owner) logscale[p * n + r] = (flags & 1) ? 0.0 : M;
   }
 }
 
@@ -210,8 +267,10 @@ static hipError_t eval_n(const System &S, const void *cws, const double *c, int6
   prof_begin(stream);
   auto kern = (flags & 4) ? (S.global_tables ? k_eval<N, float, true> : k_eval<N, float, false>)
                           : (S.global_tables ? k_eval<N, double, true> : k_eval<N, double, false>);
-  hipLaunchKernelGGL(kern, dim3(grid_for(P, gpb)), dim3(kBlock), S.lds_bytes, stream, S.dev(cws),
-                     c, P, z, s, G, logscale, flags);
+  const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
+  const size_t lds = tb + (kBlock / 64) * kEvalWaveBytes;
+  hipLaunchKernelGGL(kern, dim3(grid_for(P, gpb)), dim3(kBlock), lds, stream, S.dev(cws), c, P, z,
+                     s, G, logscale, flags, tb);
   prof_end(stream, label);
   return hipGetLastError();
 }
