@@ -189,9 +189,11 @@ int hom_track_params_default(hom_track_params *p, int precision);
  * With precision HOM_MIXED the call makes three launches: FP64 polish of the fresh start
  * points; FP32 tracking (evaluations and solves; exponent sums, state and decisions in FP64),
  * which parks every path that reaches s = 0, and at its last accepted point every path whose
- * FP32 evaluation fails, whose step falls below 1e-6 (or ds_min), that has 5 consecutive
- * rejected steps, that diverges or that has spent max_iters / 8 iterations (statuses 3 and 4,
- * internal); FP64 for the parked paths, first the rest of those tracks, then the endgames.
+ * FP32 evaluation fails at that point, whose step falls below 1e-6 (or ds_min), that has 10
+ * consecutive rejected steps or that has spent max_iters / 8 iterations (statuses 3 and 4,
+ * internal; an FP32 failure or a jump out of |Re z| <= div_re at a predicted or corrected point
+ * is a rejected step); FP64 for the parked paths, first the rest of those tracks, then the
+ * endgames.
  * Resume: calling with max_steps = k until no path is RUNNING gives the same endpoints as one
  * call; bitwise the same z and s with HOM_TRACK_EXACT_SHIFT (the counters then include one extra
  * eval+solve per resume), equal to rounding otherwise (the row shifts differ after a resume).
