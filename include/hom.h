@@ -158,7 +158,7 @@ typedef struct {
     int32_t max_steps;  /* accepted steps per call; then HOM_PATH_RUNNING */
     int32_t max_iters;  /* eval+solve cap per path per call; then HOM_PATH_MAX_ITERS */
     int32_t precision;  /* HOM_FP64 or HOM_MIXED */
-    int32_t flags;      /* 0 or HOM_TRACK_EXACT_SHIFT */
+    int32_t flags;      /* 0, HOM_TRACK_EXACT_SHIFT, HOM_TRACK_SERIAL (or both) */
     int32_t tile;       /* batched form: paths per work item = tile x lane groups per block
                            (0: the default, 4) */
 } hom_track_params;
@@ -167,6 +167,13 @@ typedef struct {
  * evaluation instead of reusing the previous evaluation's maximum.  Slower (one more pass over
  * the monomials); makes a resumed run bitwise equal to an uninterrupted one. */
 #define HOM_TRACK_EXACT_SHIFT 1
+/* hom_track_params.flags, mixed form of a single-system handle: run the FP64 re-tracks of parked
+ * paths after the FP32 launch instead of beside it.  By default a small FP64 launch on a
+ * library-owned second stream takes each parked path from a device list as soon as the FP32
+ * launch parks it; the call's stream waits for that stream before the call's last launch, so the
+ * call stays ordered on its stream.  Under stream capture the serial order is always used.  The
+ * results are the same either way (the same FP64 kernel re-tracks every parked path). */
+#define HOM_TRACK_SERIAL 2
 
 /* Fill `p` with this library's defaults for `precision`. */
 int hom_track_params_default(hom_track_params *p, int precision);
@@ -223,7 +230,9 @@ int hom_endpoint_grad(hom_system_t sys, const double *c, int64_t P, const double
  * string of at most 63 characters at names[64*i], the duration in milliseconds in ms[i], and
  * the number of eval+solves done by that launch in units[i] (-1 where not counted).  It clears
  * the list and returns the number of records written (records beyond `cap` are dropped), or a
- * negative error code.  At most 4096 records are kept.  Profiling allocates device memory.
+ * negative error code.  At most 4096 records are kept.  Switching profiling on the first time
+ * on a thread allocates its eval+solve counters (32 KiB) on the current device; the compute
+ * calls themselves allocate nothing for it.
  */
 int hom_set_profiling(int on);
 int hom_profile_read(char *names, double *ms, int64_t *units, int cap);

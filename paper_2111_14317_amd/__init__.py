@@ -29,7 +29,7 @@ CREATE_VALU = 1
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
-TRACK_EXACT_SHIFT = 1
+TRACK_EXACT_SHIFT, TRACK_SERIAL = 1, 2
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_track_params_default", "hom_track", "hom_endpoint_grad", "hom_set_profiling",

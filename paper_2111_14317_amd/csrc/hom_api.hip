@@ -5,6 +5,7 @@
 #include <climits>
 #include <cmath>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/hom.h"
@@ -14,6 +15,25 @@ namespace hom {
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
+
+// The library's second stream on each device (default priority, created on first use), for the
+// FP64 launch that runs beside the mixed form's FP32 launch.
+static constexpr int kSideBlocks = 8;  // its grid: 8 blocks of 4 waves
+static hipError_t side_stream(hipStream_t *out) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev]) {
+    e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = streams[dev];
+  return hipSuccess;
+}
 
 // ---- kernel timing ----
 struct ProfRec {
@@ -27,6 +47,9 @@ static thread_local std::vector<hipEvent_t> g_pool;
 static thread_local hipEvent_t g_open = nullptr;
 static thread_local unsigned long long *g_open_units = nullptr;
 constexpr size_t kMaxRecs = 4096;
+// one unit counter per record, allocated when profiling is switched on (no allocation between
+// launches: that could order a launch on another stream behind the running one)
+static thread_local unsigned long long *g_units_pool = nullptr;
 
 static hipEvent_t pool_get() {
   if (!g_pool.empty()) {
@@ -49,9 +72,8 @@ void prof_begin(hipStream_t stream) {
 __global__ void k_prof_zero(unsigned long long *p) { *p = 0ull; }
 
 unsigned long long *prof_units(hipStream_t stream) {
-  if (!g_prof || !g_open) return nullptr;
-  unsigned long long *u = nullptr;
-  if (hipMalloc((void **)&u, sizeof *u) != hipSuccess) return nullptr;
+  if (!g_prof || !g_open || !g_units_pool) return nullptr;
+  unsigned long long *u = g_units_pool + g_recs.size();
   hipLaunchKernelGGL(k_prof_zero, dim3(1), dim3(1), 0, stream, u);
   g_open_units = u;
   return u;
@@ -258,6 +280,9 @@ const char *hom_last_error(void) { return g_err.c_str(); }
 
 int hom_set_profiling(int on) {
   g_err.clear();
+  if (on && !g_units_pool)
+    HOM_HIP(hipMalloc((void **)&g_units_pool, kMaxRecs * sizeof *g_units_pool),
+            "hom_set_profiling: unit counters");
   g_prof = on != 0;
   return HOM_OK;
 }
@@ -279,7 +304,6 @@ int hom_profile_read(char *names, double *ms, int64_t *units, int cap) {
       if (e == hipSuccess) e = hipMemcpy(&hv, r.units, sizeof hv, hipMemcpyDeviceToHost);
       if (e != hipSuccess && err == hipSuccess) err = e;
       u = (int64_t)hv;
-      hipFree(r.units);
     }
     if (out < cap) {
       memcpy(names + 64 * out, r.label, 64);
@@ -587,7 +611,7 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     HOM_FAIL(HOM_EINVAL, "hom_track: bad precision");
   if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
       params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
-      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~HOM_TRACK_EXACT_SHIFT) ||
+      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~(HOM_TRACK_EXACT_SHIFT | HOM_TRACK_SERIAL)) ||
       params->tile < 0)
     HOM_FAIL(HOM_EINVAL, "hom_track: bad params");
   if (P == 0) return HOM_OK;
@@ -624,19 +648,58 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     HOM_HIP(e2, "hom_track: free workspace");
     return HOM_OK;
   }
-  // workspace: the device work-queue counter (+ the coefficient tables of a global-table system)
+  // The mixed form's re-tracks run beside the FP32 launch unless asked not to or captured.
+  hipStream_t side = nullptr;
+  if (mixed && !(params->flags & HOM_TRACK_SERIAL)) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HOM_HIP(hipStreamIsCapturing(st, &cs), "hom_track: capture status");
+    if (cs == hipStreamCaptureStatusNone) HOM_HIP(side_stream(&side), "hom_track: second stream");
+  }
+  // workspace: work-queue counters [0] (this stream's launches) and [1] (the side launch), the
+  // park list's counters [2..4] and, with a side launch, the park list (P entries)
+  const size_t ws_bytes = 256 + (side ? (size_t)P * sizeof(long long) : 0);
   unsigned long long *queue = nullptr;
-  HOM_HIP(hipMallocAsync((void **)&queue, 256, st), "hom_track: workspace");
+  HOM_HIP(hipMallocAsync((void **)&queue, ws_bytes, st), "hom_track: workspace");
+  long long *plist = side ? reinterpret_cast<long long *>(reinterpret_cast<char *>(queue) + 256)
+                          : nullptr;
   void *cws = nullptr;
   e = coeff_begin(h->s, c, st, &cws);
   if (e == hipSuccess && !mixed)
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr, false, queue, st);
   if (e == hipSuccess && mixed)
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_pol, false, queue, st);
+  hipEvent_t fork = nullptr, join = nullptr;
+  if (e == hipSuccess && side) {
+    e = launch_fill_i64(reinterpret_cast<long long *>(queue + 2), 0, 3, st);
+    if (e == hipSuccess) e = launch_fill_i64(plist, -1, P, st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(fork, st);
+    pr32.plist = plist;
+    pr32.pctr = queue + 2;
+  }
+  int64_t waves32 = 0;
   if (e == hipSuccess && mixed)
-    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr32, true, queue, st);
+    e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr32, true, queue, st, 0,
+                     &waves32);
+  if (e == hipSuccess && side) {  // the FP64 re-tracks beside the FP32 launch
+    TrackDev prh = pr;
+    prh.claim = 0;
+    prh.helper = 1;
+    prh.plist = plist;
+    prh.pctr = queue + 2;
+    prh.fp32_waves = (unsigned long long)waves32;
+    e = hipStreamWaitEvent(side, fork, 0);
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, prh, false, queue + 1, side,
+                       kSideBlocks);
+    if (e == hipSuccess) e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+  }
   if (e == hipSuccess && mixed)
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
+  if (fork) hipEventDestroy(fork);
+  if (join) hipEventDestroy(join);
   hipError_t e2 = coeff_end(cws, st);
   hipError_t e3 = hipFreeAsync(queue, st);
   HOM_HIP(e, "hom_track");

@@ -85,6 +85,13 @@ struct TrackDev {
   int claim;  // statuses a launch takes up: bit 0 fresh (1), bit 1 running (2), bit 2 parked
               // (3), bit 3 parked for the endgame (4)
   int polish_only;  // fresh paths stop RUNNING once polished (the mixed form's first launch)
+  // Park list of the mixed form's FP32 launch, read by a concurrent FP64 launch (null: none).
+  // plist[i] is the i-th path parked for a re-track (-1 until published); pctr[0] counts the
+  // reserved entries, pctr[1] the helper's claims, pctr[2] the FP32 launch's finished waves.
+  long long *plist;
+  unsigned long long *pctr;
+  unsigned long long fp32_waves;  // waves of the FP32 launch (all finished: no more entries)
+  int helper;                     // this FP64 launch claims from the park list
 };
 
 
@@ -106,10 +113,13 @@ hipError_t launch_eval(const System &S, const void *cws, const double *c, int64_
 hipError_t launch_step(const System &S, const void *cws, const double *c, int64_t P,
                        const double *z, const double *s, double *dE, double *dN,
                        int32_t *status, int precision, hipStream_t stream);
+// blocks: the grid (0: as many blocks as fit on the device at once); waves_out (optional): the
+// number of waves launched.
 hipError_t launch_track(const System &S, const void *cws, const double *c, int64_t P, double *z,
                         double *s, double *ds, int32_t *status, int32_t *counters,
                         const TrackDev &pr, bool mixed, unsigned long long *queue,
-                        hipStream_t stream);
+                        hipStream_t stream, int blocks = 0, int64_t *waves_out = nullptr);
+hipError_t launch_fill_i64(long long *p, long long v, int64_t n, hipStream_t stream);
 hipError_t launch_track_batch(const System &S, const double *c, int64_t P, double *z, double *s,
                               double *ds, const int32_t *sys_idx, int32_t *status,
                               int32_t *counters, const TrackDev &pr, bool mixed, void *ws,

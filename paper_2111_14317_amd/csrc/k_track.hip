@@ -54,6 +54,10 @@ constexpr int kMixedFp64Rejects = 10;
 constexpr double kMixedMinStep = 1e-6;
 // statuses of paths parked by the FP32 launch of a mixed call (internal: the call's FP64 launch
 // claims them, so they are never returned)
+// A helper launch waits at most this long (ticks of the 100 MHz constant clock) without a sign
+// of the FP32 launch's progress (a new park-list entry, a finished wave) before it stops
+// claiming; whatever it leaves is taken by the FP64 launch that follows both.
+constexpr unsigned long long kHelperPatience = 20000000ull;  // 0.2 s
 constexpr int kParked = 3;     // re-tracked in FP64 from its last accepted point
 constexpr int kParkedEnd = 4;  // at s = 0: only its endgame is left
 
@@ -111,9 +115,81 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
   int rej_run = 0;  // mixed form: consecutive rejected steps since the last accepted point
   bool exhausted = !geo.valid;
 
+  // the path's state at a claim (fresh: polish from the start point; endgame: Newton at s = 0;
+  // otherwise resumed from its last accepted point)
+  auto begin_path = [&](int64_t p, bool fresh, bool endgame) {
+    path = p;
+    zo_r = r < n ? z[2 * (p * zstride + r)] : 0.0;
+    zo_i = r < n ? z[2 * (p * zstride + r) + 1] : 0.0;
+    sZc[r] = Cx<double>{zo_r, zo_i};
+    sc = s[p];
+    sa = sc;
+    ds = fresh ? pr.ds0 : ds_io[p];
+    phase = fresh ? PH_POLISH : (endgame ? PH_END : PH_RESUME);
+    k = 0;
+    steps_here = 0;
+    iters = 0;
+    nrm_prev = 0.0;
+    need_exact = true;  // also always true with pr.exact_shift
+    rej_run = 0;
+    c0 = counters[4 * p];
+    c1 = counters[4 * p + 1];
+    c2 = counters[4 * p + 2];
+    c3 = counters[4 * p + 3];
+  };
+  // helper launch (pr.helper): this group's claimed park-list index whose entry has not been
+  // published yet, and the last change seen in the FP32 launch's progress
+  long long pend = -1;
+  unsigned long long seen = ~0ull, seen_at = 0;
+
   for (;;) {
+    if (pr.helper) {
+      // ---- claims from the park list of the concurrent FP32 launch (never blocks the wave) ----
+      if (!exhausted && path < 0) {
+        long long v = -1;
+        int done = 0;
+        if (r == 0) {
+          if (pend < 0) pend = (long long)atomicAdd(&pr.pctr[1], 1ull);
+          if (pend < P) v = __hip_atomic_load(&pr.plist[pend], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (v < 0) {
+            const unsigned long long fin32 =
+                __hip_atomic_load(&pr.pctr[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long tail =
+                __hip_atomic_load(&pr.pctr[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (fin32 >= pr.fp32_waves) {  // no more entries: this one exists iff below the tail
+              if ((unsigned long long)pend >= tail) done = 1;
+              else v = __hip_atomic_load(&pr.plist[pend], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (v < 0 && !done) {  // give up after kHelperPatience without any change seen
+              const unsigned long long now = wall_clock64(), mark = (fin32 << 32) ^ tail;
+              if (mark != seen) {
+                seen = mark;
+                seen_at = now;
+              } else if (now - seen_at > kHelperPatience) {
+                done = 1;
+              }
+            }
+          }
+        }
+        v = __shfl(v, geo.base, 64);
+        done = __shfl(done, geo.base, 64);
+        pend = __shfl(pend, geo.base, 64);
+        if (v >= 0) {
+          __threadfence();  // the parked path's state is read after its publication
+          begin_path(v, false, false);
+          pend = -1;
+        } else if (done) {
+          exhausted = true;
+        }
+      }
+      if (__all(exhausted)) break;
+      if (!__any(path >= 0)) {  // nothing to track yet: wait for the FP32 launch to park more
+        __builtin_amdgcn_s_sleep(32);
+        continue;
+      }
+    }
     // ---- claim paths for idle slots (wave-uniform loop: it shuffles) ----
-    bool need = !exhausted && path < 0;
+    bool need = !pr.helper && !exhausted && path < 0;
     while (__any(need)) {
       unsigned long long cl = 0;
       if (need && r == 0) cl = atomicAdd(queue, 1ull);
@@ -135,25 +211,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
                                           (st == kParked && (pr.claim & 4)));
           const bool endgame = second && st == kParkedEnd && (pr.claim & 8);
           if (fresh || resume || endgame) {
-            path = p;
             need = false;
-            zo_r = r < n ? z[2 * (p * zstride + r)] : 0.0;
-            zo_i = r < n ? z[2 * (p * zstride + r) + 1] : 0.0;
-            sZc[r] = Cx<double>{zo_r, zo_i};
-            sc = s[p];
-            sa = sc;
-            ds = fresh ? pr.ds0 : ds_io[p];
-            phase = fresh ? PH_POLISH : (endgame ? PH_END : PH_RESUME);
-            k = 0;
-            steps_here = 0;
-            iters = 0;
-            nrm_prev = 0.0;
-            need_exact = true;  // also always true with pr.exact_shift
-            rej_run = 0;
-            c0 = counters[4 * p];
-            c1 = counters[4 * p + 1];
-            c2 = counters[4 * p + 2];
-            c3 = counters[4 * p + 3];
+            begin_path(p, fresh, endgame);
           }
         }
       }
@@ -400,8 +459,20 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         counters[4 * p + 3] = c3;
         if (units) atomicAdd(units, (unsigned long long)iters);  // eval+solves of this launch
       }
+      if (MIXED && pr.plist && fst == kParked) {  // publish it to the concurrent FP64 launch
+        __threadfence();                          // (after every lane's writes of its state)
+        if (r == 0) {
+          const unsigned long long idx = atomicAdd(&pr.pctr[0], 1ull);
+          __hip_atomic_store(&pr.plist[idx], (long long)p, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       path = -1;
     }
+  }
+  if (MIXED && pr.plist) {  // this wave parks nothing more
+    __threadfence();
+    if ((threadIdx.x & 63) == 0) atomicAdd(&pr.pctr[2], 1ull);
   }
 }
 
@@ -425,7 +496,7 @@ template <int N>
 static hipError_t track_n(const System &S, const void *cws, const double *c, int64_t P, double *z,
                           double *s, double *ds, int32_t *status, int32_t *counters,
                           const TrackDev &pr, bool mixed, unsigned long long *queue,
-                          hipStream_t stream) {
+                          hipStream_t stream, int blocks_req, int64_t *waves_out) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
   const size_t lds = tb + track_state_bytes<N>();
   auto kern = mixed ? (S.global_tables ? k_track<N, true, true> : k_track<N, true, false>)
@@ -437,10 +508,12 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
   const int64_t gpb = (kTrackBlock / 64) * Geo<N>::G;
   int64_t blocks = (int64_t)per_cu * num_cus();
   const int64_t need = (P + gpb - 1) / gpb;
-  if (blocks > need) blocks = need > 0 ? need : 1;
+  if (blocks_req > 0) blocks = blocks_req < blocks ? blocks_req : blocks;
+  else if (blocks > need) blocks = need > 0 ? need : 1;
+  if (waves_out) *waves_out = blocks * (kTrackBlock / 64);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, queue);
   char label[64];
-  snprintf(label, sizeof label, "k_track<%d,%s>", N, mixed ? "mixed" : "fp64");
+  snprintf(label, sizeof label, "k_track<%d,%s>", N, mixed ? "mixed" : (pr.helper ? "fp64-beside" : "fp64"));
   prof_begin(stream);
   unsigned long long *units = prof_units(stream);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kTrackBlock), lds, stream, S.dev(cws), c,
@@ -470,9 +543,23 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
 hipError_t launch_track(const System &S, const void *cws, const double *c, int64_t P, double *z,
                         double *s, double *ds, int32_t *status, int32_t *counters,
                         const TrackDev &pr, bool mixed, unsigned long long *queue,
-                        hipStream_t stream) {
+                        hipStream_t stream, int blocks, int64_t *waves_out) {
   HOM_SWITCH_T(S.N, return track_n<NN>(S, cws, c, P, z, s, ds, status, counters, pr, mixed,
-                                       queue, stream))
+                                       queue, stream, blocks, waves_out))
+}
+
+__global__ void k_fill_i64(long long *p, long long v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_i64(long long *p, long long v, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t want = (n + 255) / 256;
+  const unsigned grid = (unsigned)(want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid), dim3(256), 0, stream, p, v, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------

@@ -118,6 +118,20 @@ def test_resume_bitwise(hom):
             assert mod2pi_dist(_np(st.z)[ok], _np(full.z)[ok]).max() <= 1e-12
 
 
+def test_mixed_beside_equals_serial(hom):
+    """The mixed form re-tracks its parked paths in FP64 beside the FP32 launch by default; the
+    results equal those of re-tracking them after it (TRACK_SERIAL) bit for bit, since the same
+    FP64 kernel runs every parked path from the same state."""
+    say("[track mixed beside vs serial] c2 P=16384")
+    csys, cell, z0 = W.planted_config("c2", P=16384)
+    h = hom.System.from_workload(csys)
+    a = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED, flags=hom.TRACK_SERIAL))
+    for f in ("z", "s", "ds", "status", "counters"):
+        assert np.array_equal(_np(getattr(a, f)), _np(getattr(b, f))), f
+    assert (_np(a.status) == 0).mean() >= 0.999
+
+
 def test_deterministic_and_batch_independent(hom):
     """Bitwise-equal endpoints across runs and when the path set is split."""
     say("[track determinism] c5 P=300")
