@@ -68,15 +68,17 @@ __host__ __device__ constexpr size_t track_state_bytes() {
 }
 
 // The group's current point, read from LDS into registers for one evaluation (so the replicas are
-// dead during the LU, which matters for the register budget at large N).
-template <int N>
+// dead during the LU, which matters for the register budget at large N).  Padding lanes store
+// zeros there, so the entries past n need no masking; the FP64 tracker masks them anyway, which
+// measured fewer register spills for its large groups.
+template <int N, bool MASK>
 __device__ __forceinline__ void load_point_lds(const Cx<double> *sZc, int n, double (&zr)[N],
                                                double (&zi)[N]) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const Cx<double> v = sZc[j];
-    zr[j] = j < n ? v.x : 0.0;
-    zi[j] = j < n ? v.y : 0.0;
+    zr[j] = (!MASK || j < n) ? v.x : 0.0;
+    zi[j] = (!MASK || j < n) ? v.y : 0.0;
   }
 }
 
@@ -237,7 +239,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           float absum, rf;
           double Ml = Min;
           double zr[N], zi[N];
-          load_point_lds<N>(sZc, n, zr, zi);
+          load_point_lds<N, !MIXED>(sZc, n, zr, zi);
           shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
           const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
           sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
@@ -252,7 +254,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         Cx<double> row[N + 2], ed, qd;
         double absum, rd, nEd, nNd, Ml = Min;
         double zr[N], zi[N];
-        load_point_lds<N>(sZc, n, zr, zi);
+        load_point_lds<N, !MIXED>(sZc, n, zr, zi);
         const bool okd = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
         const double h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
         const bool sd = lu_solve2<N, double>(row, r, geo.base, n, ed, qd, nEd, nNd, rd);
@@ -431,7 +433,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         }
       }
     }
-    if (geo.valid) sZc[r] = Cx<double>{zo_r, zo_i};  // read by the group's next evaluation
+    if (geo.valid)  // read by the group's next evaluation (zero for the padding unknowns)
+      sZc[r] = r < n ? Cx<double>{zo_r, zo_i} : Cx<double>{0.0, 0.0};
     if (park) {  // the last accepted point (in PH_RESUME the current point is that point)
       if (phase == PH_TRACK) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
