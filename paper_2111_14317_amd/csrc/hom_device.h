@@ -105,9 +105,26 @@ struct CoefConst {
     constexpr double c[kCoefCount] = {HOM_FP64_COEFFICIENTS};
     return c[k];
   }
+  __host__ __device__ constexpr CoefConst at(int) const { return *this; }
 };
-__host__ __device__ __forceinline__ double exp_eval(double x) {
-  constexpr CoefConst c{};
+// The same table in LDS (staged by the block), read at each use: a kernel whose registers cannot
+// also hold 35 FP64 constants takes them from there.  `off` is an opaque zero produced inside the
+// caller's loop, so that the reads stay next to their uses instead of being hoisted.
+struct CoefLds {
+  const double *K;
+  int off = 0;
+  __device__ double operator()(int k) const { return K[off + k]; }
+  __device__ CoefLds at(int o) const { return CoefLds{K, o}; }
+};
+__device__ __forceinline__ void stage_coefficients(double *sK) {  // visible after a barrier
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kCoefCount; ++i) sK[i] = CoefConst{}(i);
+  }
+}
+
+template <class Coef = CoefConst>
+__host__ __device__ __forceinline__ double exp_eval(double x, Coef c = Coef{}) {
   const double k = rint(x * kLog2e);
   double r = fma(-k, c(kCoefLn2Hi), x);
   r = fma(-k, c(kCoefLn2Lo), r);
@@ -117,8 +134,9 @@ __host__ __device__ __forceinline__ double exp_eval(double x) {
   return ldexp(p, (int)k);
 }
 
-__host__ __device__ __forceinline__ void sincos_turns(double t, double &sn, double &cs) {
-  constexpr CoefConst c{};
+template <class Coef = CoefConst>
+__host__ __device__ __forceinline__ void sincos_turns(double t, double &sn, double &cs,
+                                                      Coef c = Coef{}) {
   const double q = rint(4.0 * t);
   const double th = fma(-0.25, q, t) * c(kCoefTwoPi);
   const double t2 = th * th;
@@ -298,10 +316,30 @@ struct ShiftMargin {
   static constexpr double value = sizeof(T) == 8 ? 300.0 : 40.0;
 };
 
-template <int N, typename T>
-__device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
-                                         const double (&zi)[N], double s, Cx<T> (&row)[N + 2],
-                                         double &logM, T &absum, double &Mlag, bool exact) {
+// Where A1 reads the point: replicated registers, or the group's LDS copy read at each use (an
+// opaque zero offset, produced inside the monomial loop, keeps those reads from being hoisted
+// back into registers; the FP64 tracker trades LDS reads for the registers).
+template <int N>
+struct PointRegs {
+  const double (&zr)[N];
+  const double (&zi)[N];
+  __device__ __forceinline__ int fresh() const { return 0; }
+  __device__ __forceinline__ Cx<double> at(int j, int) const { return {zr[j], zi[j]}; }
+};
+struct PointLds {
+  const Cx<double> *z;
+  __device__ __forceinline__ int fresh() const {
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return zero;
+  }
+  __device__ __forceinline__ Cx<double> at(int j, int off) const { return z[off + j]; }
+};
+
+template <int N, typename T, class Pt, class Coef = CoefConst>
+__device__ __forceinline__ bool eval_row_at(const SysLds<N> &S, int r, const Pt &pt, double s,
+                                            Cx<T> (&row)[N + 2], double &logM, T &absum,
+                                            double &Mlag, bool exact, Coef kc = Coef{}) {
   constexpr int LD = TableLD<N>::value;
 #pragma unroll
   for (int j = 0; j < N + 2; ++j) row[j] = {T(0), T(0)};
@@ -321,9 +359,10 @@ __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double
 #pragma unroll 1
     for (int i = 0; i < mr; ++i) {
       const double *t = S.T + (i * n + r) * LD;
+      const int off = pt.fresh();
       double e = t[N] * s;
 #pragma unroll
-      for (int j = 0; j < N; ++j) e = fma(t[j], zr[j], e);
+      for (int j = 0; j < N; ++j) e = fma(t[j], pt.at(j, off).x, e);
       M = fmax(M, e);
     }
   }
@@ -333,11 +372,13 @@ __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double
 #pragma unroll 1
   for (int i = 0; i < mr; ++i) {
     const double *t = S.T + (i * n + r) * LD;
+    const int off = pt.fresh();
     double re = t[N] * s, im = 0.0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      re = fma(t[j], zr[j], re);
-      im = fma(t[j], zi[j], im);
+      const Cx<double> zj = pt.at(j, off);
+      re = fma(t[j], zj.x, re);
+      im = fma(t[j], zj.y, im);
     }
     Mnew = fmax(Mnew, re);
     double turns = im * kInv2Pi;
@@ -346,9 +387,10 @@ __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double
     Cx<T> v;
     T mag;
     if constexpr (sizeof(T) == 8) {
-      mag = exp_eval(re - M);
+      const auto kci = kc.at(off);
+      mag = exp_eval(re - M, kci);
       double sn, cs;
-      sincos_turns(turns, sn, cs);
+      sincos_turns(turns, sn, cs, kci);
       v.x = mag * (cc.x * cs - cc.y * sn);
       v.y = mag * (cc.x * sn + cc.y * cs);
       absum += mag * S.Cabs[i * n + r];
@@ -378,6 +420,13 @@ __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double
   // retries with `exact` cannot loop
   const double d = Mnew - M;
   return exact || (d <= ShiftMargin<T>::value && d >= -ShiftMargin<T>::value);
+}
+
+template <int N, typename T>
+__device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
+                                         const double (&zi)[N], double s, Cx<T> (&row)[N + 2],
+                                         double &logM, T &absum, double &Mlag, bool exact) {
+  return eval_row_at<N, T>(S, r, PointRegs<N>{zr, zi}, s, row, logM, absum, Mlag, exact);
 }
 
 // One evaluation with the exact row maximum as the shift.

@@ -94,7 +94,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
                                             int32_t *__restrict__ status,
                                             int32_t *__restrict__ counters, const TrackDev &pr,
                                             unsigned long long *queue,
-                                            unsigned long long *__restrict__ units) {
+                                            unsigned long long *__restrict__ units,
+                                            const double *kcoef) {
   const Geo<N> geo;
   const int r = geo.r;
   // per-group state in LDS: accepted point, Euler direction there, current dE and dN, current
@@ -253,9 +254,18 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       if constexpr (!MIXED) {
         Cx<double> row[N + 2], ed, qd;
         double absum, rd, nEd, nNd, Ml = Min;
-        double zr[N], zi[N];
-        load_point_lds<N, !MIXED>(sZc, n, zr, zi);
-        const bool okd = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
+        bool okd;
+        if constexpr (N >= 16) {
+          // large groups: the point and the FP64 coefficients are read from LDS at each use,
+          // since the FP64 row leaves no registers for them (C4's FP64 run: 17.0 -> 9.7 s); small
+          // ones keep them in registers (read from LDS, the 10-lane FP64 tracker ran 1.6x slower)
+          okd = eval_row_at<N, double>(S, r, PointLds{sZc}, sc, row, M, absum, Ml, need_exact,
+                                       CoefLds{kcoef});
+        } else {
+          double zr[N], zi[N];
+          load_point_lds<N, true>(sZc, n, zr, zi);
+          okd = eval_row<N, double>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
+        }
         const double h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
         const bool sd = lu_solve2<N, double>(row, r, geo.base, n, ed, qd, nEd, nNd, rd);
         const double resd = group_max<N, double>(h2, r, geo.base);  // squared relative residual
@@ -488,9 +498,12 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
             int32_t *__restrict__ counters, TrackDev pr, unsigned long long *__restrict__ queue,
             size_t table_bytes, unsigned long long *__restrict__ units) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ double kcoef[kCoefCount];
+  stage_coefficients(kcoef);
+  if constexpr (GT) __syncthreads();  // (staged tables end with a barrier of their own)
   const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n, z,
-                        s, ds_io, status, counters, pr, queue, units);
+                        s, ds_io, status, counters, pr, queue, units, kcoef);
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
@@ -585,7 +598,8 @@ __device__ __forceinline__ void batch_item(char *smem, const BatchSysDev &b,
                                            int64_t p_end, int zstride, double *z, double *s,
                                            double *ds, int32_t *status, int32_t *counters,
                                            const TrackDev &pr, unsigned long long *lq,
-                                           unsigned long long *units, size_t table_budget) {
+                                           unsigned long long *units, size_t table_budget,
+                                           const double *kcoef) {
   const SysDev sd{b.n, b.mmax, b.M, T_all + b.T_off, ints_all + b.ints_off,
                   ints_all + b.ints_off + b.n};
   // block-uniform branch (one item per block); one inlined tracker per table location, so the
@@ -594,11 +608,11 @@ __device__ __forceinline__ void batch_item(char *smem, const BatchSysDev &b,
   if (b.lds_bytes > 0) {
     const SysLds<N> S = stage_tables<N, false>(smem, sd, c + 2 * b.c_off);
     track_slots<N, MIXED>(S, b.n, slots, p_begin, p_end, zstride, z, s, ds, status, counters, pr,
-                          lq, units);
+                          lq, units, kcoef);
   } else {
     const SysLds<N> S{sd.T, Cg + b.C_off, Cabs_g + b.C_off, sd.mk, b.n, b.mmax};
     track_slots<N, MIXED>(S, b.n, slots, p_begin, p_end, zstride, z, s, ds, status, counters, pr,
-                          lq, units);
+                          lq, units, kcoef);
   }
 }
 
@@ -616,6 +630,8 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
   extern __shared__ __align__(16) char smem[];
   __shared__ unsigned long long lq;
   __shared__ long long sh_item;
+  __shared__ double kcoef[kCoefCount];
+  stage_coefficients(kcoef);  // visible after the item loop's first barrier
   const int64_t n_items = item_off[num_sys];
   for (;;) {
     __syncthreads();  // the previous item is finished by every wave before LDS is reused
@@ -640,7 +656,7 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
     const int64_t pb = sys_off[lo] + first * chunk;                                           \
     const int64_t pe = pb + chunk < sys_off[lo + 1] ? pb + chunk : sys_off[lo + 1];           \
     batch_item<NN, MIXED>(smem, b, T_all, ints_all, c, Cg, Cabs_g, pb, pe, zstride, z, s, ds,  \
-                          status, counters, pr, &lq, units, table_budget);                     \
+                          status, counters, pr, &lq, units, table_budget, kcoef);              \
     break;                                                                                    \
   }
     switch (b.N) {
