@@ -187,11 +187,29 @@ __device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restri
 // ------------------------------------------------------------------------------------------
 // BF16x3 engine
 // ------------------------------------------------------------------------------------------
-template <typename OutT>
+// LW: the liftings and the FP32 coefficients (16 bytes per monomial) are staged in LDS once per
+// block, when they fit kDenseLdsBytes; else read from global memory per term.
+constexpr size_t kDenseLdsBytes = 64 * 1024;
+
+template <typename OutT, bool LW>
 __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2)))
     k_dense_bf16(DenseDev D, const Cx<float> *__restrict__ Cf, int64_t p0, int64_t p1,
                  const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
                  double *__restrict__ logscale, int flags, unsigned long long *units) {
+  extern __shared__ __align__(16) char smem[];
+  const double *Wt = D.W;
+  const Cx<float> *Ct = Cf;
+  if constexpr (LW) {
+    double *sW = reinterpret_cast<double *>(smem);
+    Cx<float> *sC = reinterpret_cast<Cx<float> *>(sW + D.Md);
+    for (int i = threadIdx.x; i < D.Md; i += blockDim.x) {
+      sW[i] = D.W[i];
+      sC[i] = Cf[i];
+    }
+    __syncthreads();
+    Wt = sW;
+    Ct = sC;
+  }
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   const int n = D.n, nct = D.nct;
   const int64_t ntile = (p1 - p0 + 15) >> 4;
@@ -251,7 +269,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = t * 16 + row_f32(q, r);
-            const double w = D.W[i];
+            const double w = Wt[i];
             const float e = dr[r] + (float)fma(w, sp, -Mk);
             const float mag = __builtin_amdgcn_exp2f(e * (float)kLog2e);
             // phase in turns from the exact digit sums: fract(d1/512 + d2/512^2) + d3/512^3
@@ -259,7 +277,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
             ph = __builtin_amdgcn_fractf(fmaf(d2[r], 1.0f / 262144.0f, ph));
             ph = fmaf(d3[r], 1.0f / 134217728.0f, ph);
             const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-            const Cx<float> cc = Cf[i];
+            const Cx<float> cc = Ct[i];
             const float cr = cc.x * mag, ci = cc.y * mag;
             Vr[r] = cr * cs - ci * sn;
             Vi[r] = cr * sn + ci * cs;
@@ -550,10 +568,16 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
   prof_begin(stream);
   unsigned long long *units = prof_units(stream);
   const dim3 grid(dense_grid(p1 - p0)), block(kDenseBlock);
-  if (engine == 1)
-    hipLaunchKernelGGL((k_dense_bf16<OutT>), grid, block, 0, stream, S.dense, Cf, p0, p1, z, s, G,
-                       logscale, flags, units);
-  else
+  const size_t lw = (size_t)S.Md * 16;
+  if (engine == 1 && lw <= kDenseLdsBytes) {  // two blocks per CU hold the staged tables
+    const int64_t cap = 2 * (int64_t)num_cus();
+    const dim3 g2((unsigned)(grid.x < cap ? grid.x : cap));
+    hipLaunchKernelGGL((k_dense_bf16<OutT, true>), g2, block, lw, stream, S.dense, Cf, p0, p1, z,
+                       s, G, logscale, flags, units);
+  } else if (engine == 1) {
+    hipLaunchKernelGGL((k_dense_bf16<OutT, false>), grid, block, 0, stream, S.dense, Cf, p0, p1, z,
+                       s, G, logscale, flags, units);
+  } else
     hipLaunchKernelGGL((k_dense_f64<OutT>), grid, block, 0, stream, S.dense, Cd, p0, p1, z, s, G,
                        logscale, flags, units);
   prof_end(stream, engine == 1 ? "k_dense<bf16x3>" : "k_dense<fp64>");
