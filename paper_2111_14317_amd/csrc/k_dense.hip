@@ -252,13 +252,29 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       const double Mk = (double)mk;
       f32x4_t aR[2] = {zero, zero}, aI[2] = {zero, zero};
       float hr = 0.f, hi = 0.f, sr = 0.f, si = 0.f;
+      // the MFMA operand tables of the next 32 monomials are loaded one chunk ahead
+      const int ch0 = t0 >> 1, ch1 = t1 >> 1;
+      uint4 eaN[2], cbN[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        eaN[u] = D.EAb[(2 * ch0 + u) * 64 + lane];
+        cbN[u] = u < nct ? D.CBb[(ch0 * 2 + u) * 64 + lane] : uint4{0, 0, 0, 0};
+      }
 #pragma unroll 1
-      for (int ch = t0 >> 1; ch < (t1 >> 1); ++ch) {
+      for (int ch = ch0; ch < ch1; ++ch) {
         uint32_t vr[3][4], vi[3][4];  // bf16 parts hi / mid / lo of V, packed in pairs
+        const uint4 eaC[2] = {eaN[0], eaN[1]}, cbC[2] = {cbN[0], cbN[1]};
+        if (ch + 1 < ch1) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            eaN[u] = D.EAb[(2 * (ch + 1) + u) * 64 + lane];
+            if (u < nct) cbN[u] = D.CBb[((ch + 1) * 2 + u) * 64 + lane];
+          }
+        }
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
           const int t = 2 * ch + hh;
-          const bf16x8_t ea = as_bf16x8(D.EAb[t * 64 + lane]);
+          const bf16x8_t ea = as_bf16x8(eaC[hh]);
           f32x4_t dr = mfma_bf16(ea, Bzl, zero);
           dr = mfma_bf16(ea, Bzm, dr);
           dr = mfma_bf16(ea, Bzh, dr);
@@ -307,7 +323,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           if (ct < nct) {
-            const bf16x8_t cb = as_bf16x8(D.CBb[(ch * 2 + ct) * 64 + lane]);
+            const bf16x8_t cb = as_bf16x8(cbC[ct]);
             aR[ct] = mfma_bf16(r2, cb, aR[ct]);
             aR[ct] = mfma_bf16(r1, cb, aR[ct]);
             aR[ct] = mfma_bf16(r0, cb, aR[ct]);
