@@ -694,10 +694,19 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
       e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, prh, false, queue + 1, side,
                        kSideBlocks);
     if (e == hipSuccess) e = hipEventRecord(join, side);
+    // the endgames meanwhile (disjoint from the re-tracks), then whatever re-track the side
+    // launch left (none unless it stopped waiting)
+    TrackDev pr_end = pr64, pr_left = pr64;
+    pr_end.claim = 8;
+    pr_left.claim = 4;
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_end, false, queue, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
-  }
-  if (e == hipSuccess && mixed)
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_left, false, queue, st);
+  } else if (e == hipSuccess && mixed) {
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
+  }
   if (fork) hipEventDestroy(fork);
   if (join) hipEventDestroy(join);
   hipError_t e2 = coeff_end(cws, st);
