@@ -35,6 +35,7 @@ constexpr int kDenseBlock = 256;       // 4 waves; each owns one 16-point tile a
 // points per evaluation + LU round of hom_step: 4096 tiles, enough blocks for every CU; the FP32
 // rows of a round take 570 MB at n = 32
 constexpr int64_t kDenseChunk = 65536;
+constexpr int32_t kDenseRedo = 2;  // internal status between the FP32 LU and its FP64 pass
 
 __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
 
@@ -472,15 +473,12 @@ __global__ void k_dense_coeffs(DenseDev D, const double *__restrict__ c, Cx<doub
 // evaluated again on the vector units in FP64 and solved in FP64, as in the fused step.
 // ------------------------------------------------------------------------------------------
 template <int N, bool MIXED, bool GT>
-__global__ void __launch_bounds__(kDenseBlock)
+__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(MIXED && N <= 20 ? 3 : 1)))
     k_dense_lu(SysDev sd, const double *__restrict__ c, int64_t p0, int64_t p1,
                const void *__restrict__ Gws, const double *__restrict__ z,
                const double *__restrict__ s, double *__restrict__ dE, double *__restrict__ dN,
                int32_t *__restrict__ status) {
   using T = typename std::conditional<MIXED, float, double>::type;
-  extern __shared__ __align__(16) char smem[];
-  SysLds<N> S{};
-  if constexpr (MIXED) S = stage_tables<N, GT>(smem, sd, c);
   const T *Gw = static_cast<const T *>(Gws);
   const Geo<N> geo;
   const int n = sd.n, r = geo.r, ld = n + 2;
@@ -512,34 +510,57 @@ __global__ void __launch_bounds__(kDenseBlock)
     bool sing = lu_solve2<N, T>(row, r, geo.base, n, ef, qf, nE, nN, rf);
     Cx<double> e = {(double)ef.x, (double)ef.y}, qv = {(double)qf.x, (double)qf.y};
     double ratio = (double)rf;
-    if constexpr (MIXED) {
-      const bool redo = act && (sing || !(rf >= 1e-4f));
-      if (__any(redo)) {
-        double zr[N], zi[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          zr[j] = (redo && j < n) ? z[2 * (p * n + j)] : 0.0;
-          zi[j] = (redo && j < n) ? z[2 * (p * n + j) + 1] : 0.0;
-        }
-        const double sp = redo ? s[p] : 0.0;
-        Cx<double> rowd[N + 2], ed, qd;
-        double M, ad, rd, nEd, nNd;
-        eval_row_exact<N, double>(S, r, zr, zi, sp, rowd, M, ad);
-        const bool sd2 = lu_solve2<N, double>(rowd, r, geo.base, n, ed, qd, nEd, nNd, rd);
-        if (redo) {
-          e = ed;
-          qv = qd;
-          sing = sd2;
-          ratio = rd;
-        }
-      }
-    }
+    // mixed form: a point the FP32 LU cannot resolve is marked for the FP64 pass that follows
+    // (k_dense_redo), which keeps the FP64 evaluation's registers out of this kernel
+    const bool redo = MIXED && (sing || !(rf >= T(1e-4)));
     if (act) {
       if (r < n) {
         dE[2 * (p * n + r)] = e.x;
         dE[2 * (p * n + r) + 1] = e.y;
         dN[2 * (p * n + r)] = qv.x;
         dN[2 * (p * n + r) + 1] = qv.y;
+      }
+      if (r == 0) status[p] = redo ? kDenseRedo : ((sing || !(ratio >= 1e-14)) ? -1 : 0);
+    }
+  }
+}
+
+// FP64 evaluation and LU of the points the mixed form's FP32 LU marked (status kDenseRedo).
+template <int N, bool GT>
+__global__ void __launch_bounds__(kDenseBlock)
+    k_dense_redo(SysDev sd, const double *__restrict__ c, int64_t p0, int64_t p1,
+                 const double *__restrict__ z, const double *__restrict__ s,
+                 double *__restrict__ dE, double *__restrict__ dN, int32_t *__restrict__ status) {
+  extern __shared__ __align__(16) char smem[];
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
+  const Geo<N> geo;
+  const int n = sd.n, r = geo.r;
+  const int64_t gpb = (kDenseBlock / 64) * Geo<N>::G;
+  const int64_t stride = (int64_t)gridDim.x * gpb;
+  const int64_t q0 = p0 + (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g;
+  for (int64_t it = 0;; ++it) {
+    const int64_t p = q0 + it * stride;
+    const bool inside = geo.valid && p < p1;
+    if (!__any(inside)) break;
+    const bool act = inside && status[p] == kDenseRedo;
+    if (!__any(act)) continue;
+    double zr[N], zi[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      zr[j] = (act && j < n) ? z[2 * (p * n + j)] : 0.0;
+      zi[j] = (act && j < n) ? z[2 * (p * n + j) + 1] : 0.0;
+    }
+    const double sp = act ? s[p] : 0.0;
+    Cx<double> row[N + 2], e, q;
+    double M, absum, ratio, nE, nN;
+    eval_row_exact<N, double>(S, r, zr, zi, sp, row, M, absum);
+    const bool sing = lu_solve2<N, double>(row, r, geo.base, n, e, q, nE, nN, ratio);
+    if (act) {
+      if (r < n) {
+        dE[2 * (p * n + r)] = e.x;
+        dE[2 * (p * n + r) + 1] = e.y;
+        dN[2 * (p * n + r)] = q.x;
+        dN[2 * (p * n + r) + 1] = q.y;
       }
       if (r == 0) status[p] = (sing || !(ratio >= 1e-14)) ? -1 : 0;
     }
@@ -625,9 +646,16 @@ static hipError_t dense_lu_n(const System &S, const void *cws, const double *c, 
   const size_t tb = mixed ? (S.lds_bytes + 15) & ~(size_t)15 : 0;
   auto kern = mixed ? (S.global_tables ? k_dense_lu<N, true, true> : k_dense_lu<N, true, false>)
                     : k_dense_lu<N, false, false>;
-  hipLaunchKernelGGL(kern, grid, block, tb, stream, S.dev(cws), c, p0, p1, Gws, z, s, dE, dN,
+  hipLaunchKernelGGL(kern, grid, block, 0, stream, S.dev(cws), c, p0, p1, Gws, z, s, dE, dN,
                      status);
   prof_end(stream, label);
+  if (mixed) {
+    snprintf(label, sizeof label, "k_dense_redo<%d>", N);
+    prof_begin(stream);
+    auto kr = S.global_tables ? k_dense_redo<N, true> : k_dense_redo<N, false>;
+    hipLaunchKernelGGL(kr, grid, block, tb, stream, S.dev(cws), c, p0, p1, z, s, dE, dN, status);
+    prof_end(stream, label);
+  }
   return hipGetLastError();
 }
 
