@@ -153,6 +153,34 @@ def test_dense_step_ragged_and_valu_handle(hom):
                         f"valu={valu} prec={prec}")
 
 
+def test_step_mixed_redo_near_singular(hom):
+    """Mixed-form step at points whose FP32 pivot ratio is below the redo threshold: equation 1 is
+    equation 0 with its coefficients perturbed by 1e-6, so every Jacobian has two nearly equal rows
+    (pivot ratio 1e-9 .. 3e-6, condition 1e7 .. 3e10).  The FP32 LU alone would lose every digit
+    there; the FP64 redo must give directions within kappa * 1e-13 of the oracle, on both the
+    matrix-core handle and the vector-unit handle."""
+    say("[mixed redo] n=20 m=64 P=40, near-duplicate equations")
+    rng = np.random.default_rng(23)
+    n = 20
+    sy = W.random_system(n, 64, W._uniform_exps(-3, 3), "unit", 12, rng, rng, rng)
+    A, w, c = sy.A.copy(), sy.w.copy(), sy.c.copy()
+    e0, e1 = sy.equation(0), sy.equation(1)
+    A[e1], w[e1] = A[e0], w[e0]
+    c[e1] = c[e0] * (1 + 1e-6 * (rng.standard_normal(64) + 1j * rng.standard_normal(64)))
+    ns = W.System(n, sy.m.copy(), A, w, c)
+    z, s = W.random_points(n, 40, rng)
+    oE, oN, ost, ratio = oracle.step(ns, ns.c, z, s)
+    kappa = np.abs(cond_inf(ns, ns.c, z, s))
+    assert ratio.max() < 1e-4 and (ost == 0).all() and kappa.min() > 1e6
+    for valu in (False, True):
+        h = hom.System.from_workload(ns, valu=valu)
+        dE, dN, st = hom.step(h, ns.c, z, s, precision=hom.MIXED)
+        e = np.maximum(_dir_err(_np(dE), oE), _dir_err(_np(dN), oN))
+        say(f"  valu={valu}: max err/kappa {(e / kappa).max():.3e}")
+        assert (_np(st) == 0).all()
+        assert (e <= kappa * 1e-13).all()
+
+
 def test_dense_full_size_sampled(hom):
     """The full 262144-point n = 32 workload in both matrix-core engines; a seeded sample of 128
     points against the oracle (G of the whole batch is 4.6 GB on the device)."""
