@@ -96,6 +96,9 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
                                             unsigned long long *queue,
                                             unsigned long long *__restrict__ units,
                                             const double *kcoef) {
+  // The side launch's re-tracks are the mixed form's critical path once the FP32 launch drains:
+  // its waves take issue priority over the FP32 launch's waves on the SIMDs they share.
+  if (pr.helper) __builtin_amdgcn_s_setprio(2);
   const Geo<N> geo;
   const int r = geo.r;
   // per-group state in LDS: accepted point, Euler direction there, current dE and dN, current
