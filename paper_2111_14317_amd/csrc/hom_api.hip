@@ -656,7 +656,7 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     if (cs == hipStreamCaptureStatusNone) HOM_HIP(side_stream(&side), "hom_track: second stream");
   }
   // workspace: work-queue counters [0] (this stream's launches) and [1] (the side launch), the
-  // park list's counters [2..4] and, with a side launch, the park list (P entries)
+  // park list's counters [2..5] and, with a side launch, the park list (P entries)
   const size_t ws_bytes = 256 + (side ? (size_t)P * sizeof(long long) : 0);
   unsigned long long *queue = nullptr;
   HOM_HIP(hipMallocAsync((void **)&queue, ws_bytes, st), "hom_track: workspace");
@@ -670,7 +670,7 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_pol, false, queue, st);
   hipEvent_t fork = nullptr, join = nullptr;
   if (e == hipSuccess && side) {
-    e = launch_fill_i64(reinterpret_cast<long long *>(queue + 2), 0, 3, st);
+    e = launch_fill_i64(reinterpret_cast<long long *>(queue + 2), 0, 4, st);
     if (e == hipSuccess) e = launch_fill_i64(plist, -1, P, st);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
@@ -699,6 +699,8 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     TrackDev pr_end = pr64, pr_left = pr64;
     pr_end.claim = 8;
     pr_left.claim = 4;
+    pr_left.pctr = queue + 2;
+    pr_left.drained_exit = 1;
     if (e == hipSuccess)
       e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_end, false, queue, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);

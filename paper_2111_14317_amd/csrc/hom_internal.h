@@ -87,11 +87,13 @@ struct TrackDev {
   int polish_only;  // fresh paths stop RUNNING once polished (the mixed form's first launch)
   // Park list of the mixed form's FP32 launch, read by a concurrent FP64 launch (null: none).
   // plist[i] is the i-th path parked for a re-track (-1 until published); pctr[0] counts the
-  // reserved entries, pctr[1] the helper's claims, pctr[2] the FP32 launch's finished waves.
+  // reserved entries, pctr[1] the helper's claims, pctr[2] the FP32 launch's finished waves,
+  // pctr[3] the entries the helper took up (and tracked to their end).
   long long *plist;
   unsigned long long *pctr;
   unsigned long long fp32_waves;  // waves of the FP32 launch (all finished: no more entries)
   int helper;                     // this FP64 launch claims from the park list
+  int drained_exit;  // launched after both: return at once when the helper took every entry
 };
 
 

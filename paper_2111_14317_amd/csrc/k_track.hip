@@ -182,6 +182,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         pend = __shfl(pend, geo.base, 64);
         if (v >= 0) {
           __threadfence();  // the parked path's state is read after its publication
+          if (r == 0) atomicAdd(&pr.pctr[3], 1ull);
           begin_path(v, false, false);
           pend = -1;
         } else if (done) {
@@ -500,6 +501,10 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
             double *__restrict__ s, double *__restrict__ ds_io, int32_t *__restrict__ status,
             int32_t *__restrict__ counters, TrackDev pr, unsigned long long *__restrict__ queue,
             size_t table_bytes, unsigned long long *__restrict__ units) {
+  // The mixed form's last launch, after the side launch: with every parked path taken up there
+  // (the counters are final: both earlier launches have completed), no path is left to claim.
+  // Every thread reads the same values, so whole blocks return before any barrier.
+  if (pr.drained_exit && pr.pctr[3] == pr.pctr[0]) return;
   extern __shared__ __align__(16) char smem[];
   __shared__ double kcoef[kCoefCount];
   stage_coefficients(kcoef);
