@@ -200,7 +200,8 @@ int hom_track_params_default(hom_track_params *p, int precision);
  * consecutive rejected steps or that has spent max_iters / 8 iterations (statuses 3 and 4,
  * internal; an FP32 failure or a jump out of |Re z| <= div_re at a predicted or corrected point
  * is a rejected step); FP64 for the parked paths, first the rest of those tracks, then the
- * endgames.
+ * endgames (single-system handles: the re-tracks run on the library's second stream while the
+ * FP32 launch runs and the endgames follow it, unless HOM_TRACK_SERIAL is set).
  * Resume: calling with max_steps = k until no path is RUNNING gives the same endpoints as one
  * call; bitwise the same z and s with HOM_TRACK_EXACT_SHIFT (the counters then include one extra
  * eval+solve per resume), equal to rounding otherwise (the row shifts differ after a resume).
