@@ -12,7 +12,9 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   step            pinned: LAPACK solve, Cramer's rule, closed-form directions of binomial systems
   track           pinned: closed-form binomial paths, mixed-volume root count, residuals
   endpoint_grad   pinned: central finite differences of re-solved endpoints
-  residual        pinned: zeros at binomial roots, scale invariance
+  residual        pinned: hand-worked exact values (tests/golden/residual_2x2.json), exact
+                  rational arithmetic at rational points, the closed form at perturbed binomial
+                  roots, zeros at roots, coefficient-scale and branch invariance
 """
 from __future__ import annotations
 
@@ -57,7 +59,9 @@ def _load():
         _lib.oracle_track.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
         _lib.oracle_residual.argtypes = [i32, P, P, P, i64, P, P, i32]
         _lib.oracle_endpoint_grad.argtypes = [i32, P, P, P, P, i64, P, P, P]
-        _lib.oracle_endpoint_grad.restype = i32
+        for name in ("oracle_eval", "oracle_step", "oracle_track", "oracle_residual",
+                     "oracle_endpoint_grad"):
+            getattr(_lib, name).restype = i32
     return _lib
 
 
@@ -65,7 +69,18 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
+NMAX = 32  # the C oracle keeps per-point arrays on the stack
+
+
+def _checked(code):
+    if code < 0:
+        raise ValueError("oracle: n must be in [1, 32]")
+    return code
+
+
 def _sys_arrays(sys):
+    if not 1 <= sys.n <= NMAX:
+        raise ValueError(f"oracle: n = {sys.n} outside [1, {NMAX}]")
     return (np.ascontiguousarray(sys.m, np.int32), np.ascontiguousarray(sys.A, np.int8),
             np.ascontiguousarray(sys.w, np.float64))
 
@@ -87,8 +102,8 @@ def eval(sys, c, z, s, scaled=True, threads=None, with_den=False):
     G = np.zeros((P, n, n + 2), np.complex128)
     L = np.zeros((P, n), np.float64)
     den = np.zeros((P, n, n + 2), np.float64) if with_den else None
-    lib.oracle_eval(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), int(scaled),
-                    _ptr(G), _ptr(L), _ptr(den), threads or default_threads())
+    _checked(lib.oracle_eval(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s),
+                             int(scaled), _ptr(G), _ptr(L), _ptr(den), threads or default_threads()))
     return (G, L, den) if with_den else (G, L)
 
 
@@ -105,8 +120,8 @@ def step(sys, c, z, s, threads=None):
     dN = np.zeros((P, n), np.complex128)
     st = np.zeros(P, np.int32)
     ratio = np.zeros(P, np.float64)
-    lib.oracle_step(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(dE),
-                    _ptr(dN), _ptr(st), _ptr(ratio), threads or default_threads())
+    _checked(lib.oracle_step(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(dE),
+                             _ptr(dN), _ptr(st), _ptr(ratio), threads or default_threads()))
     return dE, dN, st, ratio
 
 
@@ -151,8 +166,9 @@ def track(sys, c, z0, s0, params: TrackParams | None = None, status=None, ds=Non
     st = np.full(P, START, np.int32) if status is None else np.array(status, np.int32)
     cnt = np.zeros((P, 4), np.int32)
     d, i = params.arrays()
-    lib.oracle_track(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(ds),
-                     _ptr(d), _ptr(i), _ptr(st), _ptr(cnt), threads or default_threads())
+    _checked(lib.oracle_track(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s),
+                              _ptr(ds), _ptr(d), _ptr(i), _ptr(st), _ptr(cnt),
+                              threads or default_threads()))
     return z, s, ds, st, cnt
 
 
@@ -163,8 +179,8 @@ def residual(sys, c, z, threads=None):
     c = np.ascontiguousarray(c, np.complex128)
     z = np.ascontiguousarray(z, np.complex128).reshape(-1, sys.n)
     out = np.zeros(z.shape[0], np.float64)
-    lib.oracle_residual(sys.n, _ptr(m), _ptr(A), _ptr(c), z.shape[0], _ptr(z), _ptr(out),
-                        threads or default_threads())
+    _checked(lib.oracle_residual(sys.n, _ptr(m), _ptr(A), _ptr(c), z.shape[0], _ptr(z),
+                                 _ptr(out), threads or default_threads()))
     return out
 
 
@@ -177,6 +193,6 @@ def endpoint_grad(sys, c, z_end, grad_x):
     z = np.ascontiguousarray(z_end, np.complex128).reshape(-1, sys.n)
     g = np.ascontiguousarray(grad_x, np.complex128).reshape(-1, sys.n)
     out = np.zeros(sys.M, np.complex128)
-    ns = lib.oracle_endpoint_grad(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), z.shape[0], _ptr(z),
-                                  _ptr(g), _ptr(out))
+    ns = _checked(lib.oracle_endpoint_grad(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), z.shape[0],
+                                           _ptr(z), _ptr(g), _ptr(out)))
     return out, int(ns)

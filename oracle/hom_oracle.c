@@ -41,6 +41,8 @@
 
 typedef double complex cplx;
 
+/* Largest n: per-point work arrays live on the stack.  Every entry point returns -1 (and
+ * touches no output) for n outside [1, OR_NMAX]. */
 #define OR_NMAX 32
 
 /* ---------------------------------------------------------------------------------------- */
@@ -129,15 +131,17 @@ static void eval_point(int n, const int32_t *m, const int8_t *A, const double *w
     }
 }
 
-void oracle_eval(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
-                 int64_t P, const double *z, const double *s, int scaled, double *G,
-                 double *logscale, double *den, int threads) {
+int oracle_eval(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                int64_t P, const double *z, const double *s, int scaled, double *G,
+                double *logscale, double *den, int threads) {
+    if (n < 1 || n > OR_NMAX) return -1;
 #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
     for (int64_t p = 0; p < P; p++) {
         eval_point(n, m, A, w, (const cplx *)c, (const cplx *)z + p * n, s[p], scaled,
                    (cplx *)G + p * n * (n + 2), logscale ? logscale + p * n : NULL,
                    den ? den + p * n * (n + 2) : NULL);
     }
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------------------- */
@@ -216,9 +220,10 @@ static int step_point(int n, const int32_t *m, const int8_t *A, const double *w,
     return st;
 }
 
-void oracle_step(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
-                 int64_t P, const double *z, const double *s, double *dE, double *dN,
-                 int32_t *status, double *ratio, int threads) {
+int oracle_step(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                int64_t P, const double *z, const double *s, double *dE, double *dN,
+                int32_t *status, double *ratio, int threads) {
+    if (n < 1 || n > OR_NMAX) return -1;
 #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
     for (int64_t p = 0; p < P; p++) {
         double r;
@@ -227,6 +232,7 @@ void oracle_step(int n, const int32_t *m, const int8_t *A, const double *w, cons
         status[p] = st ? -1 : 0;
         if (ratio) ratio[p] = r;
     }
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------------------- */
@@ -363,9 +369,10 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
     *ds_io = ds;
 }
 
-void oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
-                  int64_t P, double *z, double *s, double *ds, const double *dparams,
-                  const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {
+int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                 int64_t P, double *z, double *s, double *ds, const double *dparams,
+                 const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {
+    if (n < 1 || n > OR_NMAX) return -1;
     or_params pr;
     pr.ds0 = dparams[0];
     pr.ds_max = dparams[1];
@@ -385,6 +392,7 @@ void oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, con
     for (int64_t p = 0; p < P; p++)
         track_path(n, m, A, w, (const cplx *)c, &pr, (cplx *)z + p * n, s + p, ds + p,
                    status + p, counters + 4 * p);
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------------------- */
@@ -392,8 +400,9 @@ void oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, con
 /* ---------------------------------------------------------------------------------------- */
 
 /* relative backward error r(x) = max_k |f_k(x)| / sum_a |c_{k,a} x^a| at t = 1 */
-void oracle_residual(int n, const int32_t *m, const int8_t *A, const double *c, int64_t P,
-                     const double *z, double *out, int threads) {
+int oracle_residual(int n, const int32_t *m, const int8_t *A, const double *c, int64_t P,
+                    const double *z, double *out, int threads) {
+    if (n < 1 || n > OR_NMAX) return -1;
 #pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
     for (int64_t p = 0; p < P; p++) {
         const cplx *zp = (const cplx *)z + p * n;
@@ -418,15 +427,17 @@ void oracle_residual(int n, const int32_t *m, const int8_t *A, const double *c, 
         }
         out[p] = r;
     }
+    return 0;
 }
 
 /* grad_c (M complex) of L(x*) with upstream g = dL/dRe x + i dL/dIm x at the endpoints.
  * Per path: J_x^H nu = -g with J_x = J_z diag(e^{-z}), i.e. J_z^H nu = -conj(x) . g; then
  * grad c_{k,a} += nu_k conj(x^a).  Paths are summed in index order.  Returns the number of
- * paths whose Jacobian was singular (they are skipped). */
+ * paths whose Jacobian was singular (they are skipped), or -1 when n is out of range. */
 int oracle_endpoint_grad(int n, const int32_t *m, const int8_t *A, const double *w,
                          const double *c, int64_t P, const double *z_end, const double *grad_x,
                          double *grad_c) {
+    if (n < 1 || n > OR_NMAX) return -1;
     int M = 0;
     for (int k = 0; k < n; k++) M += m[k];
     cplx *gc = (cplx *)grad_c;
