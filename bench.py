@@ -84,13 +84,14 @@ def _workload(P):
     return csys, z0
 
 
-def run_form(hom, torch, h, csys, z0, precision, steps, warmup):
-    """Returns dict with rate, ms/step, ok fraction, mean evals/path and kernel timings."""
+def run_form(hom, torch, h, csys, z0, precision, steps, warmup, **overrides):
+    """Returns dict with rate, ms/step, ok fraction, mean evals/path, kernel timings and the last
+    step's endpoints and statuses."""
     dev = "cuda"
     P = z0.shape[0]
     c = torch.tensor(csys.c, dtype=torch.complex128, device=dev)
     z_init = torch.tensor(z0, dtype=torch.complex128, device=dev)
-    params = hom.default_params(precision)
+    params = hom.default_params(precision, **overrides)
     total = warmup + steps
     states = []
     for _ in range(total):
@@ -130,10 +131,87 @@ def run_form(hom, torch, h, csys, z0, precision, steps, warmup):
     launches = {}
     for name, _, _ in prof:
         launches[name] = launches.get(name, 0) + 1
+    last = states[total - 1]
     return dict(rate=evals / sec, ms_per_step=1e3 * sec / steps, ok_frac=min(ok),
                 evals_per_path=sum(evals_per_path) / len(evals_per_path),
                 evals_per_step=evals / steps, kernels=kern, units=units,
-                launches={k: v / steps for k, v in launches.items()}, paths_per_s=P * steps / sec)
+                launches={k: v / steps for k, v in launches.items()}, paths_per_s=P * steps / sec,
+                z_end=last.z.cpu().numpy(), status=last.status.cpu().numpy())
+
+
+def status_hist(st):
+    import numpy as np
+    u, c = np.unique(st, return_counts=True)
+    return {str(int(a)): int(b) for a, b in zip(u, c)}
+
+
+def _mod2pi_dist(a, b):
+    import numpy as np
+    dre = np.abs(a.real - b.real)
+    dim = np.abs(np.angle(np.exp(1j * (a.imag - b.imag))))
+    return np.maximum(dre, dim).max(axis=-1)
+
+
+def _projection(z, seed=20211129):
+    """fixed random positive weights on Re z_j, cos Im z_j, sin Im z_j; points within d of each
+    other (max modulus, mod 2 pi i) project to within W d"""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n = z.shape[1]
+    wr, wc, ws = (rng.uniform(0.5, 1.0, n) for _ in range(3))
+    return z.real @ wr + np.cos(z.imag) @ wc + np.sin(z.imag) @ ws, wr.sum() + wc.sum() + ws.sum()
+
+
+def _nearest(a, b, radius=1e-6):
+    """smallest max-modulus distance (mod 2 pi i) from each row of a to the rows of b within
+    `radius` (inf when none)"""
+    import numpy as np
+    out = np.full(len(a), np.inf)
+    if len(a) == 0 or len(b) == 0:
+        return out
+    pa, W = _projection(a)
+    pb, _ = _projection(b)
+    order = np.argsort(pb)
+    pbs = pb[order]
+    lo = np.searchsorted(pbs, pa - radius * W, side="left")
+    hi = np.searchsorted(pbs, pa + radius * W, side="right")
+    for k in range(int((hi - lo).max(initial=0))):
+        idx = np.nonzero(hi - lo > k)[0]
+        out[idx] = np.minimum(out[idx], _mod2pi_dist(a[idx], b[order[lo[idx] + k]]))
+    return out
+
+
+def _distinct(z, tol=1e-8):
+    """number of endpoints pairwise more than tol apart (mod 2 pi i)"""
+    import numpy as np
+    if len(z) == 0:
+        return 0
+    p, W = _projection(z)
+    order = np.argsort(p)
+    ps = p[order]
+    dup = np.zeros(len(z), bool)
+    k = 1
+    while k < len(ps):
+        near = ps[k:] - ps[:-k] <= tol * W
+        if not near.any():
+            break
+        i, j = order[:-k][near], order[k:][near]
+        dup[np.maximum(i, j)[_mod2pi_dist(z[i], z[j]) <= tol]] = True
+        k += 1
+    return int((~dup).sum())
+
+
+def compare_endpoints(a, b):
+    """Form a's endpoints against form b's, path by path (same start points): how many paths end
+    OK in both, the largest distance over them, how many differ by more than 1e-10 (a path that
+    ended on another path's root), and the distinct OK endpoints of each form."""
+    import numpy as np
+    both = (a["status"] == 0) & (b["status"] == 0)
+    d = _mod2pi_dist(a["z_end"][both], b["z_end"][both])
+    return {"both_ok": int(both.sum()), "max_dist": float(d.max()) if both.any() else 0.0,
+            "differ_gt_1e-10": int((d > 1e-10).sum()),
+            "distinct_ok": [_distinct(a["z_end"][a["status"] == 0]),
+                            _distinct(b["z_end"][b["status"] == 0])]}
 
 
 # dense-support configuration: n = 32, 128 monomials per equation, 262144 points (eval and step)
@@ -253,6 +331,212 @@ def run_eval_n10(hom, torch, P=65536, reps=5):
     return out
 
 
+def flops_step(n, M):
+    """Algorithmic flops of one eval + 2-rhs solve of a system with n unknowns and M monomials
+    (the same count as FLOPS_PER_UNIT, which is flops_step(10, 120))."""
+    a1 = 2 * (2 * n + 1) * M
+    a2 = 6 * M
+    a3 = M * (4 * (n + 1) + 2)
+    lu = sum((n - 1 - j) * (6 + 8 * (n + 1 - j)) for j in range(n)) + 8 * n
+    back = 2 * (n * (n - 1) // 2 * 8 + 6 * n)
+    return a1 + a2 + a3 + lu + back, a1
+
+
+def run_c4(hom, torch, reps=3):
+    """The batched form at full size: 256 planted-cell systems (n in 6..24, 8..64 monomials per
+    equation), ~5.8e5 paths in one persistent launch sequence per call.  Per form: the work-item
+    size from the autotuner, the call captured in a HIP graph and replayed `reps` times (the state
+    is reset between replays, outside the timed region), eval+solve/s, paths/s, OK fraction, the
+    batched kernel's time (library events, eager run) and its algorithmic TFLOP/s."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2111_14317_amd import autotune
+    t0 = time.perf_counter()
+    sy = W.c4_systems()
+    systems, starts = [s_ for s_, _, _ in sy], [z0 for _, _, z0 in sy]
+    z, idx, c = W.stack_batch(systems, starts)
+    gen_s = time.perf_counter() - t0
+    P = len(z)
+    b = hom.Batch(systems)
+    dev = "cuda"
+    ct = torch.tensor(c, dtype=torch.complex128, device=dev)
+    it = torch.tensor(idx, dtype=torch.int32, device=dev)
+    z0 = torch.tensor(z, dtype=torch.complex128, device=dev)
+    fl = np.array([flops_step(s_.n, int(np.sum(s_.m)))[0] for s_ in systems], np.float64)
+    fl64 = np.array([flops_step(s_.n, int(np.sum(s_.m)))[1] for s_ in systems], np.float64)
+    out = {"systems": len(systems), "paths": P, "generate_s": gen_s}
+    for name, prec in (("mixed", hom.MIXED), ("fp64", hom.FP64)):
+        tile, times = autotune.tune(hom, b, ct, z, -32.0, idx, prec, candidates=(1, 2, 4, 8),
+                                    sample_every=8, cache_path=None)
+        params = hom.default_params(prec, tile=tile)
+        st = hom.TrackState(z0.clone(), torch.full((P,), -32.0, dtype=torch.float64, device=dev),
+                            torch.zeros(P, dtype=torch.float64, device=dev),
+                            torch.full((P,), hom.PATH_START, dtype=torch.int32, device=dev),
+                            torch.zeros((P, 4), dtype=torch.int32, device=dev))
+
+        def reset():
+            st.z.copy_(z0)
+            st.s.fill_(-32.0)
+            st.ds.zero_()
+            st.status.fill_(hom.PATH_START)
+            st.counters.zero_()
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # a first launch off the default stream before capture
+            hom.track(b, ct, None, None, params, state=st, sys_idx=it)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        reset()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            hom.track(b, ct, None, None, params, state=st, sys_idx=it)
+        torch.cuda.synchronize()
+        wall = []
+        evals = ok = None
+        for _ in range(reps):
+            reset()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t)
+            cnt = st.counters[:, 3].cpu().numpy().astype(np.float64)
+            evals = cnt.sum()
+            stt = st.status.cpu().numpy()
+            ok = float((stt == 0).mean())
+        del g
+        # kernel time of the same call, eager, with the library's events
+        reset()
+        torch.cuda.synchronize()
+        hom.profile_read()
+        hom.set_profiling(True)
+        hom.track(b, ct, None, None, params, state=st, sys_idx=it)
+        torch.cuda.synchronize()
+        hom.set_profiling(False)
+        prof = hom.profile_read()
+        kms = {}
+        for kname, ms, u in prof:
+            kms[kname] = kms.get(kname, 0.0) + ms
+        cnt = st.counters[:, 3].cpu().numpy().astype(np.float64)
+        work = float(np.sum(cnt * fl[idx]))
+        work64 = float(np.sum(cnt * fl64[idx]))
+        kern = f"k_track_batch<{name}>"
+        ktot = sum(kms.values())
+        peak = PEAK_FP64 if name == "fp64" else work / (work64 / PEAK_FP64 + (work - work64) / PEAK_FP32)
+        rec = {"tile": tile, "tile_ms": times, "graph_replay_s": min(wall),
+               "eval_solve_per_s": evals / min(wall), "paths_per_s": P / min(wall), "ok_frac": ok,
+               "statuses": status_hist(stt), "evals_per_path": evals / P, "kernels_ms": kms,
+               "tflops_algorithmic": work / (ktot * 1e-3) / 1e12,
+               "frac_of_peak": work / (ktot * 1e-3) / peak, "peak_tflops": peak / 1e12,
+               "dominant_kernel": kern}
+        out[name] = rec
+        print(f"# c4 {name}: tile {tile}, {min(wall):.3f} s/replay, {rec['eval_solve_per_s']:.3e} "
+              f"{UNIT}, ok {ok:.5f}, {rec['tflops_algorithmic']:.2f} TFLOP/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
+def run_c5(hom, torch, P=16384, reps=3):
+    """The differentiation workload: 16384 paths of the n = 8 system tracked in FP64, loss
+    sum |x*|^2; the adjoint gradient w.r.t. all 128 coefficients in FP64 and in the mixed form:
+    kernel ms (library events), paths/s, and the per-entry error against the oracle's gradient."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    csys, cell, z0 = W.planted_config("c5", P=P)
+    h = hom.System.from_workload(csys)
+    st = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64))
+    z, sg = st.z.cpu().numpy(), st.status.cpu().numpy()
+    ok = sg == 0
+    g = np.where(ok[:, None], 2 * np.exp(z), 0)
+    ref, _ = oracle.endpoint_grad(csys, csys.c, z, g)
+    out = {"paths": P, "ok_frac": float(ok.mean())}
+    dev = "cuda"
+    zt = torch.tensor(z, dtype=torch.complex128, device=dev)
+    gt = torch.tensor(g, dtype=torch.complex128, device=dev)
+    ct = torch.tensor(csys.c, dtype=torch.complex128, device=dev)
+    for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
+        got = hom.endpoint_grad(h, ct, zt, gt, precision=prec)
+        torch.cuda.synchronize()
+        hom.profile_read()
+        hom.set_profiling(True)
+        for _ in range(reps):
+            got = hom.endpoint_grad(h, ct, zt, gt, precision=prec)
+        torch.cuda.synchronize()
+        hom.set_profiling(False)
+        ms = sum(t for _, t, _ in hom.profile_read()) / reps
+        err = np.abs(got.cpu().numpy() - ref) / np.abs(ref)
+        out[name] = {"kernel_ms": ms, "paths_per_s": P / (ms * 1e-3),
+                     "max_rel_err_per_entry_vs_oracle": float(err.max())}
+        print(f"# c5 grad {name}: {ms:.3f} ms, max per-entry rel err {err.max():.2e}",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def error_table(hom, torch, csys, mixed, fp64, ora_z, ora_st, c5):
+    """The mixed form's error against the FP64 oracle, per result: G (scaled componentwise metric)
+    and d_E, d_N (relative, where kappa <= 1e2; and the largest error / kappa anywhere) on 4096
+    random points of the n = 10 system; endpoints (the last timed step of each form against the
+    oracle's endpoints of the CPU-baseline sample, as sets; and the FP64 form path by path); the
+    adjoint gradient (per entry, from the differentiation leg)."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    sys_, z, s = W.config_system("c2", P=4096)
+    h = hom.System.from_workload(sys_)
+    G, L = hom.eval(h, sys_.c, z, s, flags=hom.EVAL_FP32)
+    Go, Lo, den = oracle.eval(sys_, sys_.c, z, s, with_den=True)
+    Gg = G.cpu().numpy() * np.exp(L.cpu().numpy() - Lo)[:, :, None]
+    scale = np.maximum(den, 1e-30 * den[:, :, -1:])
+    eG = float((np.abs(Gg - Go) / np.where(scale > 0, scale, 1.0)).max())
+    dE, dN, st = hom.step(h, sys_.c, z, s, precision=hom.MIXED)
+    oE, oN, ost, _ = oracle.step(sys_, sys_.c, z, s)
+    kap = np.abs(np.linalg.cond(Go[:, :, :sys_.n], p=np.inf))
+
+    def rel(a, b):
+        return np.abs(a - b).max(1) / np.abs(b).max(1)
+
+    eE, eN = rel(dE.cpu().numpy(), oE), rel(dN.cpu().numpy(), oN)
+    well = (kap <= 1e2) & (ost == 0)
+    fin = ost == 0
+    out = {"G_scaled_max": eG,
+           "dE_rel_max_kappa_le_1e2": float(eE[well].max()),
+           "dN_rel_max_kappa_le_1e2": float(eN[well].max()),
+           "dE_over_kappa_max": float((eE / kap)[fin].max()),
+           "dN_over_kappa_max": float((eN / kap)[fin].max()), "points": len(z),
+           "points_kappa_le_1e2": int(well.sum())}
+    n0 = len(ora_z)
+    for name, form in (("mixed", mixed), ("fp64", fp64)):
+        zg, sg = form["z_end"][:n0], form["status"][:n0]
+        okg = sg == 0
+        d = _nearest(zg[okg], ora_z[ora_st == 0])
+        both = okg & (ora_st == 0)
+        out[f"endpoints_{name}"] = {
+            "paths": n0, "ok": int(okg.sum()), "set_max_dist": float(d.max()),
+            "path_by_path_max_dist": float(_mod2pi_dist(zg[both], ora_z[both]).max()),
+            "paths_on_another_root": int((_mod2pi_dist(zg[both], ora_z[both]) > 1e-10).sum())}
+    if c5:
+        out["grad_rel_max_per_entry"] = c5["mixed"]["max_rel_err_per_entry_vs_oracle"]
+        out["grad_rel_max_per_entry_fp64_form"] = c5["fp64"]["max_rel_err_per_entry_vs_oracle"]
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(csys, z0, target_s=15.0):
     """The oracle (unchanged) tracking a bounded sample of the same paths on the host cores."""
     import numpy as np
@@ -266,11 +550,19 @@ def cpu_baseline(csys, z0, target_s=15.0):
     dt = time.perf_counter() - t
     n1 = int(min(len(z0), max(n0, n0 * target_s / max(dt, 1e-3))))
     t = time.perf_counter()
-    _, _, _, st, cnt = oracle.track(csys, csys.c, z0[:n1], -32.0, threads=threads)
+    ze, _, _, st, cnt = oracle.track(csys, csys.c, z0[:n1], -32.0, threads=threads)
     dt = time.perf_counter() - t
+    # one thread on a smaller sample (about 5 s)
+    n2 = max(16, int(n1 * 5.0 / max(dt * threads, 1e-3)))
+    t = time.perf_counter()
+    _, _, _, _, cnt1 = oracle.track(csys, csys.c, z0[:n2], -32.0, threads=1)
+    dt1 = time.perf_counter() - t
     return {"value": float(cnt[:, 3].sum()) / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"first {n1} of the {len(z0)} paths, tracked s=-32..0 in FP64 "
-                      f"({dt:.1f} s, {float(np.mean(st == 0)):.4f} ok)"}
+                      f"({dt:.1f} s, {float(np.mean(st == 0)):.4f} ok)",
+            "single_thread_value": float(cnt1[:, 3].sum()) / dt1,
+            "single_thread_sample": f"first {n2} paths, {dt1:.1f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}, ze, st
 
 
 def main():
@@ -283,6 +575,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-support (n=32, m=128) eval/step leg")
     ap.add_argument("--dense-points", type=int, default=262144)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (256 systems) leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also write and then read one 512 MiB buffer (scales the HBM counters)")
     args = ap.parse_args()
@@ -305,8 +599,12 @@ def main():
         assert total > 0
         del buf
     res = {}
-    for name, prec in (("fp64", hom.FP64), ("mixed", hom.MIXED)):
-        res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup)
+    # the plain FP64 form, the mixed form, and an FP64 control at the mixed form's corrector
+    # tolerance (separates the effect of the precision from that of the tolerance)
+    legs = (("fp64", hom.FP64, {}), ("mixed", hom.MIXED, {}),
+            ("fp64_tol_track_1e-5", hom.FP64, {"tol_track": 1e-5}))
+    for name, prec, kw in legs:
+        res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup, **kw)
         print(f"# {name}: {res[name]['rate']:.4e} {UNIT}, {res[name]['ms_per_step']:.2f} ms/step, "
               f"ok {res[name]['ok_frac']:.5f}, {res[name]['evals_per_path']:.1f} evals/path, "
               f"kernels {res[name]['kernels']}", file=sys.stderr, flush=True)
@@ -320,11 +618,18 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(), "kernel": dom, "kernel_ms": dom_ms,
                 "kernel_units": dom_units, "flops_per_unit": FLOPS_PER_UNIT}
-    f64 = res["fp64"]
-    f64_dom = f"k_track<{N_EQ},fp64>"
-    f64_frac = None
-    if f64_dom in f64["kernels"]:
-        f64_frac = f64["units"][f64_dom] * FLOPS_PER_UNIT / (f64["kernels"][f64_dom] * 1e-3) / PEAK_FP64
+
+    def form_rec(r):
+        f64_dom = f"k_track<{N_EQ},fp64>"
+        frac = None
+        if f64_dom in r["kernels"]:
+            frac = r["units"][f64_dom] * FLOPS_PER_UNIT / (r["kernels"][f64_dom] * 1e-3) / PEAK_FP64
+        return {"value": r["rate"], "ms_per_step": r["ms_per_step"], "ok_frac": r["ok_frac"],
+                "statuses_last_step": status_hist(r["status"]),
+                "evals_per_path": r["evals_per_path"], "paths_per_s": r["paths_per_s"],
+                "kernels_ms": r["kernels"], "kernel_units": r["units"],
+                "roofline_frac_fp64_peak": frac}
+
     out = {
         "metric": METRIC, "value": mixed["rate"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
@@ -333,22 +638,28 @@ def main():
                                "system (12 monomials/eq, exponents U[-3,3], unit-circle coeffs, "
                                "lifting {0,0,U{1..63}}) from s=-32 to 0, FP64 endgame",
                    "paths": args.paths, "n": N_EQ, "monomials_per_eq": M_EQ},
-        "fp64": {"value": res["fp64"]["rate"], "ms_per_step": res["fp64"]["ms_per_step"],
-                 "ok_frac": res["fp64"]["ok_frac"], "evals_per_path": res["fp64"]["evals_per_path"],
-                 "paths_per_s": res["fp64"]["paths_per_s"], "kernels_ms": res["fp64"]["kernels"],
-                 "kernel_units": res["fp64"]["units"], "roofline_frac_fp64_peak": f64_frac},
-        "mixed": {"value": mixed["rate"], "ms_per_step": mixed["ms_per_step"],
-                  "ok_frac": mixed["ok_frac"], "evals_per_path": mixed["evals_per_path"],
-                  "paths_per_s": mixed["paths_per_s"], "kernels_ms": mixed["kernels"],
-                  "kernel_units": mixed["units"]},
+        "fp64": form_rec(res["fp64"]),
+        "mixed": form_rec(mixed),
+        "fp64_tol_track_1e-5": form_rec(res["fp64_tol_track_1e-5"]),
+        "endpoints_mixed_vs_fp64": compare_endpoints(mixed, res["fp64"]),
+        "endpoints_fp64_tol_track_1e-5_vs_fp64": compare_endpoints(res["fp64_tol_track_1e-5"],
+                                                                   res["fp64"]),
         "roofline": roof,
     }
+    out["mixed"].pop("roofline_frac_fp64_peak")
     if not args.no_dense:
         out["eval_step_n10_65536_points"] = run_eval_n10(hom, torch, P=65536)
         out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)
         out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
+    if not args.no_batch:
+        out["batch_c4"] = run_c4(hom, torch)
+    c5 = None
+    if not args.no_grad:
+        c5 = out["grad_c5"] = run_c5(hom, torch)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(csys, z0)
+        out["cpu_baseline"], ora_z, ora_st = cpu_baseline(csys, z0)
+        out["mixed_error_vs_oracle"] = error_table(hom, torch, csys, mixed, res["fp64"], ora_z,
+                                                   ora_st, c5)
     print(json.dumps(out), flush=True)
 
 

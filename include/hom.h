@@ -152,13 +152,18 @@ typedef struct {
     double res_tol;    /* endpoint OK when max_k |h_k| / sum_a |c_a x^a| <= res_tol */
     double div_re;     /* |Re z_j| > div_re => HOM_PATH_DIVERGED */
     double sing_ratio; /* min|pivot| / max|pivot| below this => singular */
+    double tol_predict; /* a predicted point whose first ||dz_newton||_inf exceeds this is
+                           rejected before any correction (the predictor left the corrector's
+                           trust region, where the Newton iteration may converge to another
+                           path); the step is halved */
     int32_t max_polish; /* Newton iterations allowed at the start point */
     int32_t max_newton; /* corrector iterations per step before the step is rejected */
     int32_t max_end;    /* endgame Newton iterations */
     int32_t max_steps;  /* accepted steps per call; then HOM_PATH_RUNNING */
     int32_t max_iters;  /* eval+solve cap per path per call; then HOM_PATH_MAX_ITERS */
     int32_t precision;  /* HOM_FP64 or HOM_MIXED */
-    int32_t flags;      /* 0, HOM_TRACK_EXACT_SHIFT, HOM_TRACK_SERIAL (or both) */
+    int32_t flags;      /* 0 or any of HOM_TRACK_EXACT_SHIFT, HOM_TRACK_SERIAL,
+                           HOM_TRACK_SIDE_NOWAIT */
     int32_t tile;       /* batched form: paths per work item = tile x lane groups per block
                            (0: the default, 4) */
 } hom_track_params;
@@ -174,6 +179,11 @@ typedef struct {
  * call stays ordered on its stream.  Under stream capture the serial order is always used.  The
  * results are the same either way (the same FP64 kernel re-tracks every parked path). */
 #define HOM_TRACK_SERIAL 2
+/* hom_track_params.flags, mixed form with the FP64 re-tracks beside the FP32 launch: the side
+ * launch stops claiming as soon as it finds no parked path waiting (instead of waiting up to
+ * 0.2 s for the FP32 launch to park more); the call's last launch re-tracks whatever it left.
+ * The results are the same; this exercises that hand-over (tests) and is otherwise slower. */
+#define HOM_TRACK_SIDE_NOWAIT 4
 
 /* Fill `p` with this library's defaults for `precision`. */
 int hom_track_params_default(hom_track_params *p, int precision);

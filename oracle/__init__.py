@@ -138,6 +138,7 @@ class TrackParams:
     res_tol: float = 1e-10
     div_re: float = 40.0
     sing_ratio: float = 1e-14
+    tol_predict: float = 1e-2
     max_polish: int = 10
     max_newton: int = 3
     max_end: int = 8
@@ -146,7 +147,8 @@ class TrackParams:
 
     def arrays(self):
         d = np.array([self.ds0, self.ds_max, self.ds_min, self.tol_polish, self.tol_track,
-                      self.tol_end, self.res_tol, self.div_re, self.sing_ratio], np.float64)
+                      self.tol_end, self.res_tol, self.div_re, self.sing_ratio,
+                      self.tol_predict], np.float64)
         i = np.array([self.max_polish, self.max_newton, self.max_end, self.max_steps,
                       self.max_iters], np.int32)
         return d, i

@@ -248,6 +248,7 @@ typedef struct {
     double res_tol;     /* endpoint accepted when the relative residual <= res_tol */
     double div_re;      /* |Re z_j| > div_re => diverged */
     double sing_ratio;  /* min/max |pivot| below this => singular */
+    double tol_predict; /* a predicted point whose first correction exceeds this is rejected */
     int max_polish, max_newton, max_end, max_steps, max_iters;
 } or_params;
 
@@ -316,7 +317,10 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
         }
         if (phase == PH_END) goto endgame;
 
-        /* PH_TRACK: corrector */
+        /* PH_TRACK: corrector.  At the predicted point itself (no correction yet) the Newton
+         * step measures how far the predictor left the path: beyond tol_predict the point may
+         * lie nearer another path than its own, so the step is rejected before any correction */
+        if (k == 0 && nrm > pr->tol_predict) goto reject;
         if (nrm <= pr->tol_track) {
             /* accept the evaluated point */
             for (int j = 0; j < n; j++) { za[j] = z[j]; dEa[j] = dE[j]; }
@@ -369,6 +373,8 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
     *ds_io = ds;
 }
 
+/* Track P paths.  dparams: ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re,
+ * sing_ratio, tol_predict; iparams: max_polish, max_newton, max_end, max_steps, max_iters. */
 int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
                  int64_t P, double *z, double *s, double *ds, const double *dparams,
                  const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {
@@ -383,6 +389,7 @@ int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, cons
     pr.res_tol = dparams[6];
     pr.div_re = dparams[7];
     pr.sing_ratio = dparams[8];
+    pr.tol_predict = dparams[9];
     pr.max_polish = iparams[0];
     pr.max_newton = iparams[1];
     pr.max_end = iparams[2];

@@ -29,7 +29,7 @@ CREATE_VALU = 1
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
-TRACK_EXACT_SHIFT, TRACK_SERIAL = 1, 2
+TRACK_EXACT_SHIFT, TRACK_SERIAL, TRACK_SIDE_NOWAIT = 1, 2, 4
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_track_params_default", "hom_track", "hom_endpoint_grad", "hom_set_profiling",
@@ -47,7 +47,7 @@ class TrackParams(ctypes.Structure):
                 ("tol_polish", ctypes.c_double), ("tol_track", ctypes.c_double),
                 ("tol_end", ctypes.c_double), ("res_tol", ctypes.c_double),
                 ("div_re", ctypes.c_double), ("sing_ratio", ctypes.c_double),
-                ("max_polish", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("tol_predict", ctypes.c_double), ("max_polish", ctypes.c_int32), ("max_newton", ctypes.c_int32),
                 ("max_end", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("tile", ctypes.c_int32)]

@@ -578,6 +578,7 @@ int hom_track_params_default(hom_track_params *p, int precision) {
   p->res_tol = 1e-10;
   p->div_re = 40.0;
   p->sing_ratio = 1e-14;
+  p->tol_predict = 1e-2;
   p->max_polish = 10;
   p->max_newton = 3;
   p->max_end = 8;
@@ -591,31 +592,53 @@ int hom_track_params_default(hom_track_params *p, int precision) {
 
 static TrackDev to_dev(const hom_track_params *p) {
   return TrackDev{p->ds0,        p->ds_max,     p->ds_min,  p->tol_polish, p->tol_track,
-                  p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->max_polish,
+                  p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->tol_predict,
+                  p->max_polish,
                   p->max_newton, p->max_end,    p->max_steps, p->max_iters,
                   (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3, 0};
+}
+
+// Checks of hom_track's arguments shared by its allocation-free variant.  Returns HOM_OK (then
+// *nothing_to_do tells whether P == 0) or an error code with the message set.
+static int check_track_args(const char *fn, hom_system_t h, const double *c, int64_t P,
+                            const double *z, const double *s, const double *ds,
+                            const int32_t *sys_idx, const hom_track_params *params,
+                            const int32_t *status, const int32_t *counters, bool *nothing_to_do) {
+  const std::string f(fn);
+  *nothing_to_do = false;
+  if (!h) HOM_FAIL(HOM_EINVAL, f + ": NULL handle");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, f + ": P < 0");
+  if (!params) HOM_FAIL(HOM_EINVAL, f + ": NULL params");
+  const bool batch = h->s.num_sys > 0;
+  if (!batch && sys_idx)
+    HOM_FAIL(HOM_EINVAL, f + ": sys_idx must be NULL for a single-system handle");
+  if (batch && P > 0 && !sys_idx) HOM_FAIL(HOM_EINVAL, f + ": a batch handle needs sys_idx");
+  if (params->precision != HOM_FP64 && params->precision != HOM_MIXED)
+    HOM_FAIL(HOM_EINVAL, f + ": bad precision");
+  if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
+      !(params->tol_predict > 0) ||
+      params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
+      params->max_steps < 0 || params->max_iters < 1 ||
+      (params->flags & ~(HOM_TRACK_EXACT_SHIFT | HOM_TRACK_SERIAL | HOM_TRACK_SIDE_NOWAIT)) ||
+      params->tile < 0)
+    HOM_FAIL(HOM_EINVAL, f + ": bad params");
+  if (P == 0) {
+    *nothing_to_do = true;
+    return HOM_OK;
+  }
+  if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, f + ": NULL array");
+  return HOM_OK;
 }
 
 int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
               const int32_t *sys_idx, const hom_track_params *params, int32_t *status,
               int32_t *counters, hom_stream_t stream) {
   g_err.clear();
-  if (!h) HOM_FAIL(HOM_EINVAL, "hom_track: NULL handle");
-  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_track: P < 0");
-  if (!params) HOM_FAIL(HOM_EINVAL, "hom_track: NULL params");
+  bool none = false;
+  const int rc = check_track_args("hom_track", h, c, P, z, s, ds, sys_idx, params, status,
+                                  counters, &none);
+  if (rc != HOM_OK || none) return rc;
   const bool batch = h->s.num_sys > 0;
-  if (!batch && sys_idx)
-    HOM_FAIL(HOM_EINVAL, "hom_track: sys_idx must be NULL for a single-system handle");
-  if (batch && P > 0 && !sys_idx) HOM_FAIL(HOM_EINVAL, "hom_track: a batch handle needs sys_idx");
-  if (params->precision != HOM_FP64 && params->precision != HOM_MIXED)
-    HOM_FAIL(HOM_EINVAL, "hom_track: bad precision");
-  if (!(params->ds0 > 0) || !(params->ds_max > 0) || !(params->ds_min >= 0) ||
-      params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
-      params->max_steps < 0 || params->max_iters < 1 || (params->flags & ~(HOM_TRACK_EXACT_SHIFT | HOM_TRACK_SERIAL)) ||
-      params->tile < 0)
-    HOM_FAIL(HOM_EINVAL, "hom_track: bad params");
-  if (P == 0) return HOM_OK;
-  if (!c || !z || !s || !ds || !status || !counters) HOM_FAIL(HOM_EINVAL, "hom_track: NULL array");
   hipStream_t st = (hipStream_t)stream;
   const TrackDev pr = to_dev(params);
   const bool mixed = params->precision == HOM_MIXED;
@@ -689,11 +712,20 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     prh.plist = plist;
     prh.pctr = queue + 2;
     prh.fp32_waves = (unsigned long long)waves32;
+    prh.patience = (params->flags & HOM_TRACK_SIDE_NOWAIT) ? 0ull : kSidePatience;
+    // Once the side launch may be queued, the call's stream must not free the workspace (or
+    // reuse the coefficient tables) before it ends, whatever fails afterwards: the stream waits
+    // for `join`, or, if that event could not be recorded, the host waits for the side stream.
+    bool side_queued = false, joined = false;
     e = hipStreamWaitEvent(side, fork, 0);
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
+      side_queued = true;
       e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, prh, false, queue + 1, side,
                        kSideBlocks);
-    if (e == hipSuccess) e = hipEventRecord(join, side);
+      const hipError_t er = hipEventRecord(join, side);
+      joined = er == hipSuccess;
+      if (e == hipSuccess) e = er;
+    }
     // the endgames meanwhile (disjoint from the re-tracks), then whatever re-track the side
     // launch left (none unless it stopped waiting)
     TrackDev pr_end = pr64, pr_left = pr64;
@@ -703,7 +735,14 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
     pr_left.drained_exit = 1;
     if (e == hipSuccess)
       e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_end, false, queue, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    if (side_queued) {
+      const hipError_t ew = joined ? hipStreamWaitEvent(st, join, 0) : hipStreamSynchronize(side);
+      if (e == hipSuccess) e = ew;
+      if (ew != hipSuccess && joined) {  // the stream could not be ordered: wait on the host
+        const hipError_t es = hipStreamSynchronize(side);
+        if (e == hipSuccess) e = es;
+      }
+    }
     if (e == hipSuccess)
       e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_left, false, queue, st);
   } else if (e == hipSuccess && mixed) {

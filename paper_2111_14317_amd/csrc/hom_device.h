@@ -298,6 +298,45 @@ __device__ SysLds<N> stage_tables(char *smem, const SysDev &sd, const double *__
   return SysLds<N>{sT, sC, sA, sM, n, mmax};
 }
 
+// Tables of the FP32 evaluation (the mixed form), staged beside the FP64 ones: the exponents as
+// f16 (exact: |a| <= 127), H16<N> halves per (monomial, equation) record, which the row
+// accumulation feeds to mixed f16 x f32 FMAs without conversions, and {Re c, Im c, |c|, w} as
+// float.  Null pointers: the evaluation converts the FP64 tables instead.
+template <int N>
+struct H16 {
+  static constexpr int value = (N + 3) / 4 * 4;  // 8-byte records: conflict-free for N <= 12
+};
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+template <int N>
+struct F32Tables {
+  const half4_t *Th;  // [mmax][n][H16 / 4]
+  const float4 *Cf;   // [mmax][n]
+};
+template <int N>
+__host__ __device__ constexpr size_t lds_f32_bytes(int n, int mmax) {
+  return (size_t)mmax * n * (H16<N>::value * 2 + 16);
+}
+
+// Stage the FP32 tables at `dst` (16-byte aligned, lds_f32_bytes) from the staged FP64 tables
+// (which must be visible: call after stage_tables); ends with a barrier.
+template <int N>
+__device__ F32Tables<N> stage_f32_tables(char *dst, const SysLds<N> &S) {
+  constexpr int LD = TableLD<N>::value, H = H16<N>::value;
+  const int n = S.n, recs = S.mmax * S.n;
+  float4 *Cf = reinterpret_cast<float4 *>(dst);
+  _Float16 *Th = reinterpret_cast<_Float16 *>(Cf + recs);
+  for (int idx = threadIdx.x; idx < recs; idx += blockDim.x) {
+    const double *t = S.T + idx * LD;  // record (i, r) = idx: the same order
+    const Cx<double> cc = S.C[idx];
+    Cf[idx] = make_float4((float)cc.x, (float)cc.y, (float)S.Cabs[idx], (float)t[N]);
+#pragma unroll
+    for (int j = 0; j < H; ++j) Th[idx * H + j] = (_Float16)(j < N ? (float)t[j] : 0.0f);
+  }
+  (void)n;
+  __syncthreads();
+  return F32Tables<N>{reinterpret_cast<const half4_t *>(Th), Cf};
+}
+
 // ------------------------------------------------------------------------------------------
 // A1-A3: one row of [J_z | H_s | H] at (z, s), scaled by e^{-M_r}
 // ------------------------------------------------------------------------------------------
@@ -339,7 +378,8 @@ struct PointLds {
 template <int N, typename T, class Pt, class Coef = CoefConst>
 __device__ __forceinline__ bool eval_row_at(const SysLds<N> &S, int r, const Pt &pt, double s,
                                             Cx<T> (&row)[N + 2], double &logM, T &absum,
-                                            double &Mlag, bool exact, Coef kc = Coef{}) {
+                                            double &Mlag, bool exact, Coef kc = Coef{},
+                                            const F32Tables<N> *ft = nullptr) {
   constexpr int LD = TableLD<N>::value;
 #pragma unroll
   for (int j = 0; j < N + 2; ++j) row[j] = {T(0), T(0)};
@@ -380,7 +420,7 @@ __device__ __forceinline__ bool eval_row_at(const SysLds<N> &S, int r, const Pt 
       re = fma(t[j], zj.x, re);
       im = fma(t[j], zj.y, im);
     }
-    Mnew = fmax(Mnew, re);
+    Mnew = re > Mnew ? re : Mnew;  // (ignores a NaN like fmax, without its canonicalisation)
     double turns = im * kInv2Pi;
     turns -= rint(turns);  // phase in turns, [-1/2, 1/2]
     const Cx<double> cc = S.C[i * n + r];
@@ -398,20 +438,46 @@ __device__ __forceinline__ bool eval_row_at(const SysLds<N> &S, int r, const Pt 
       mag = __builtin_amdgcn_exp2f((float)((re - M) * kLog2e));
       const float tf = (float)turns;
       const float sn = __builtin_amdgcn_sinf(tf), cs = __builtin_amdgcn_cosf(tf);
-      const float cx = (float)cc.x, cy = (float)cc.y;
-      v.x = mag * (cx * cs - cy * sn);
-      v.y = mag * (cx * sn + cy * cs);
-      absum += mag * (float)S.Cabs[i * n + r];
+      if (ft) {  // FP32 tables: no conversions
+        const float4 cw = ft->Cf[i * n + r];
+        v.x = mag * (cw.x * cs - cw.y * sn);
+        v.y = mag * (cw.x * sn + cw.y * cs);
+        absum += mag * cw.z;
+      } else {
+        const float cx = (float)cc.x, cy = (float)cc.y;
+        v.x = mag * (cx * cs - cy * sn);
+        v.y = mag * (cx * sn + cy * cs);
+        absum += mag * (float)S.Cabs[i * n + r];
+      }
     }
+    if (sizeof(T) == 4 && ft) {
+      const half4_t *th = ft->Th + (i * n + r) * (H16<N>::value / 4);
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const T a = (T)t[j];
-      row[j].x = fma(a, v.x, row[j].x);
-      row[j].y = fma(a, v.y, row[j].y);
+      for (int q = 0; q < H16<N>::value / 4; ++q) {
+        const half4_t a4 = th[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 4 * q + e;
+          if (j < N) {
+            row[j].x = fmaf((float)a4[e], (float)v.x, (float)row[j].x);
+            row[j].y = fmaf((float)a4[e], (float)v.y, (float)row[j].y);
+          }
+        }
+      }
+      const float wv = ft->Cf[i * n + r].w;
+      row[N].x = fma((T)wv, v.x, row[N].x);
+      row[N].y = fma((T)wv, v.y, row[N].y);
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const T a = (T)t[j];
+        row[j].x = fma(a, v.x, row[j].x);
+        row[j].y = fma(a, v.y, row[j].y);
+      }
+      const T wv = (T)t[N];
+      row[N].x = fma(wv, v.x, row[N].x);
+      row[N].y = fma(wv, v.y, row[N].y);
     }
-    const T wv = (T)t[N];
-    row[N].x = fma(wv, v.x, row[N].x);
-    row[N].y = fma(wv, v.y, row[N].y);
     row[N + 1].x += v.x;
     row[N + 1].y += v.y;
   }
@@ -425,8 +491,10 @@ __device__ __forceinline__ bool eval_row_at(const SysLds<N> &S, int r, const Pt 
 template <int N, typename T>
 __device__ __forceinline__ bool eval_row(const SysLds<N> &S, int r, const double (&zr)[N],
                                          const double (&zi)[N], double s, Cx<T> (&row)[N + 2],
-                                         double &logM, T &absum, double &Mlag, bool exact) {
-  return eval_row_at<N, T>(S, r, PointRegs<N>{zr, zi}, s, row, logM, absum, Mlag, exact);
+                                         double &logM, T &absum, double &Mlag, bool exact,
+                                         const F32Tables<N> *ft = nullptr) {
+  return eval_row_at<N, T>(S, r, PointRegs<N>{zr, zi}, s, row, logM, absum, Mlag, exact,
+                           CoefConst{}, ft);
 }
 
 // One evaluation with the exact row maximum as the shift.
@@ -509,10 +577,13 @@ __device__ __forceinline__ bool lu_solve2(Cx<T> (&row)[N + 2], int r, int base, 
     const Cx<T> xe = shfl_cx(e, src), xq = shfl_cx(q, src);
     row[N] = cfma(row[N], row[j], xe);
     row[N + 1] = cfma(row[N + 1], row[j], xq);
-    if (r == j) {
-      myE = xe;
-      myN = xq;
-    }
+    // lane j keeps unknown j: selects, not a branch (a branch per column costs more than the
+    // four selects in exec-mask bookkeeping)
+    const bool mine = r == j;
+    myE.x = mine ? xe.x : myE.x;
+    myE.y = mine ? xe.y : myE.y;
+    myN.x = mine ? xq.x : myN.x;
+    myN.y = mine ? xq.y : myN.y;
   }
   // norms over the true unknowns: squared moduli, a group maximum, one square root
   const T ae = r < n ? myE.x * myE.x + myE.y * myE.y : T(0);

@@ -78,7 +78,8 @@ struct System {
 
 // Tracker constants as the kernels see them.
 struct TrackDev {
-  double ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re, sing_ratio;
+  double ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re, sing_ratio,
+      tol_predict;
   int max_polish, max_newton, max_end, max_steps, max_iters;
   int exact_shift;
   int tile;
@@ -94,7 +95,12 @@ struct TrackDev {
   unsigned long long fp32_waves;  // waves of the FP32 launch (all finished: no more entries)
   int helper;                     // this FP64 launch claims from the park list
   int drained_exit;  // launched after both: return at once when the helper took every entry
+  // helper: ticks of the 100 MHz constant clock it waits without a sign of the FP32 launch's
+  // progress (a new park-list entry, a finished wave) before it stops claiming; whatever it
+  // leaves is re-tracked by the FP64 launch that follows both
+  unsigned long long patience;
 };
+constexpr unsigned long long kSidePatience = 20000000ull;  // 0.2 s
 
 
 void set_error(const std::string &msg);

@@ -17,33 +17,21 @@
 
 namespace hom {
 
-template <int N, bool MIXED, bool GT>
-__global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__restrict__ c,
-                                                   int64_t P0, int64_t Pc,
-                                                   const double *__restrict__ z,
-                                                   const double *__restrict__ gx,
-                                                   double *__restrict__ work, size_t table_bytes) {
-  using T = typename std::conditional<MIXED, float, double>::type;
-  constexpr int LD = TableLD<N>::value;
-  extern __shared__ __align__(16) char smem[];
-  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
-  const Geo<N> geo;
-  const int n = sd.n, r = geo.r, M = sd.M;
-  Cx<T> *tile = reinterpret_cast<Cx<T> *>(smem + table_bytes) + (geo.valid ? geo.g : 0) * N * N;
-  const int64_t p_loc = (int64_t)blockIdx.x * Geo<N>::G + geo.g;
-  const bool act = geo.valid && p_loc < Pc;
-  const int64_t p = P0 + (act ? p_loc : 0);
-  double zr[N], zi[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    zr[j] = j < n ? z[2 * (p * n + j)] : 0.0;
-    zi[j] = j < n ? z[2 * (p * n + j) + 1] : 0.0;
-  }
+// mu = -(Js^H)^{-1} b for one path, in precision T: evaluate J_z at t = 1 (lane r: row r),
+// transpose it through the group's LDS tile so that lane j holds row j of Js^H, then the group LU.
+// Returns the singular flag; ratio is the pivot ratio, Mr the row shift.  Every lane of the wave
+// must call it (it shuffles).
+template <int N, typename T>
+__device__ __forceinline__ bool adjoint_solve(const SysLds<N> &S, const Geo<N> &geo, int n,
+                                              const double (&zr)[N], const double (&zi)[N],
+                                              Cx<double> b, Cx<T> *tile, Cx<double> &mu,
+                                              double &ratio, double &Mr) {
+  const int r = geo.r;
   Cx<T> row[N + 2];
-  double Mr;
   T absum;
   eval_row_exact<N, T>(S, r, zr, zi, 0.0, row, Mr, absum);
-  // transpose J_z through LDS: lane j takes conj of column j
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // earlier reads of the tile are done
+  __builtin_amdgcn_wave_barrier();
   if (geo.valid) {
 #pragma unroll
     for (int j = 0; j < N; ++j) tile[r * N + j] = row[j];
@@ -56,26 +44,86 @@ __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__re
     const Cx<T> v = geo.valid ? tile[j * N + r] : Cx<T>{T(j == r), T(0)};
     rh[j] = {v.x, -v.y};
   }
+  rh[N] = {(T)b.x, (T)b.y};
+  rh[N + 1] = {T(0), T(0)};
+  Cx<T> m, unused;
+  double nE, nN;
+  T rt;
+  bool sing = lu_solve2<N, T>(rh, r, geo.base, n, m, unused, nE, nN, rt);
+  sing |= !(nE <= INFINITY);
+  mu = {(double)m.x, (double)m.y};
+  ratio = (double)rt;
+  return sing;
+}
+
+// The mixed form solves in FP32 and redoes in FP64 the paths whose FP32 pivot ratio is below
+// this (or that are singular in FP32), as the mixed step does: near a singular endpoint the FP32
+// solve would carry an error of about kappa * 6e-8 into the gradient.
+constexpr double kGradRedoRatio = 1e-4;
+// A path whose (final) pivot ratio is below this is singular and contributes nothing, as in
+// hom_step.
+constexpr double kGradSingRatio = 1e-14;
+
+template <int N, bool MIXED, bool GT>
+__global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__restrict__ c,
+                                                   int64_t P0, int64_t Pc,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ gx,
+                                                   double *__restrict__ work, size_t table_bytes,
+                                                   double sing_ratio) {
+  constexpr int LD = TableLD<N>::value;
+  extern __shared__ __align__(16) char smem[];
+  const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
+  const Geo<N> geo;
+  const int n = sd.n, r = geo.r, M = sd.M;
+  // the group's transpose tile, sized for FP64 (the mixed form's redo uses it too)
+  char *tile_b = smem + table_bytes + (size_t)(geo.valid ? geo.g : 0) * N * N * sizeof(Cx<double>);
+  const int64_t p_loc = (int64_t)blockIdx.x * Geo<N>::G + geo.g;
+  const bool act = geo.valid && p_loc < Pc;
+  const int64_t p = P0 + (act ? p_loc : 0);
+  double zr[N], zi[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    zr[j] = j < n ? z[2 * (p * n + j)] : 0.0;
+    zi[j] = j < n ? z[2 * (p * n + j) + 1] : 0.0;
+  }
   // right-hand side conj(x_r) g_r (zero on padding unknowns)
-  Cx<T> b = {T(0), T(0)};
+  Cx<double> b = {0.0, 0.0};
   if (act && r < n) {
     const double mag = exp(z[2 * (p * n + r)]);
     double sn, cs;
     sincos(-z[2 * (p * n + r) + 1], &sn, &cs);
     const Cx<double> xc = {mag * cs, mag * sn};  // conj(x_r)
     const Cx<double> g = {gx[2 * (p * n + r)], gx[2 * (p * n + r) + 1]};
-    const Cx<double> bb = cmul(xc, g);
-    b = {(T)bb.x, (T)bb.y};
+    b = cmul(xc, g);
   }
-  rh[N] = b;
-  rh[N + 1] = {T(0), T(0)};
-  Cx<T> mu, unused;
-  double nE, nN;
-  T ratio;
-  const bool sing = lu_solve2<N, T>(rh, r, geo.base, n, mu, unused, nE, nN, ratio);
-  // lu_solve2 returns -(Js^H)^{-1} b, which is mu.  Contributions of equation r's monomials.
+  Cx<double> mu;
+  double ratio, Mr;
+  bool sing;
+  if constexpr (MIXED) {
+    sing = adjoint_solve<N, float>(S, geo, n, zr, zi, b, reinterpret_cast<Cx<float> *>(tile_b), mu,
+                                   ratio, Mr);
+    const bool redo = sing || !(ratio >= kGradRedoRatio);  // uniform within a group
+    if (__any(redo)) {  // the whole wave runs the FP64 solve; only the flagged groups keep it
+      Cx<double> mu64;
+      double ratio64, Mr64;
+      const bool sing64 = adjoint_solve<N, double>(S, geo, n, zr, zi, b,
+                                                   reinterpret_cast<Cx<double> *>(tile_b), mu64,
+                                                   ratio64, Mr64);
+      if (redo) {
+        mu = mu64;
+        ratio = ratio64;
+        Mr = Mr64;
+        sing = sing64;
+      }
+    }
+  } else {
+    sing = adjoint_solve<N, double>(S, geo, n, zr, zi, b, reinterpret_cast<Cx<double> *>(tile_b), mu,
+                                    ratio, Mr);
+  }
+  // mu = -(Js^H)^{-1} b.  Contributions of equation r's monomials.
   if (!act || r >= n) return;
-  const bool ok = !sing && nE <= INFINITY;
+  const bool ok = !sing && ratio >= sing_ratio;
   const int mr = S.mk[r];
   double *out = work + 2 * (p_loc * (int64_t)M);
   for (int i = 0; i < mr; ++i) {
@@ -99,7 +147,7 @@ __global__ void __launch_bounds__(64) k_grad_paths(SysDev sd, const double *__re
       sincos_turns(turns, sn, cs);
       E = {mag * cs, -mag * sn};
     }
-    Cx<double> v = ok ? cmul(Cx<double>{(double)mu.x, (double)mu.y}, E) : Cx<double>{0.0, 0.0};
+    Cx<double> v = ok ? cmul(mu, E) : Cx<double>{0.0, 0.0};
     const int q = sd.off[r] + i;
     out[2 * q] = v.x;
     out[2 * q + 1] = v.y;
@@ -152,7 +200,7 @@ static hipError_t grad_n(const System &S, const void *cws, const double *c, int6
                          const double *gx, double *grad, int precision, double *work,
                          size_t work_elems, hipStream_t stream) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
-  const size_t tile = (size_t)Geo<N>::G * N * N * (precision == 1 ? 8 : 16);
+  const size_t tile = (size_t)Geo<N>::G * N * N * sizeof(Cx<double>);
   const int64_t part_elems = 2 * (int64_t)kRedT * S.M;
   int64_t Pc = ((int64_t)work_elems - part_elems) / (2 * (int64_t)S.M);
   if (Pc < 1) return hipErrorInvalidValue;
@@ -172,7 +220,7 @@ static hipError_t grad_n(const System &S, const void *cws, const double *c, int6
                     ? (S.global_tables ? k_grad_paths<N, true, true> : k_grad_paths<N, true, false>)
                     : (S.global_tables ? k_grad_paths<N, false, true> : k_grad_paths<N, false, false>);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), tb + tile, stream, S.dev(cws), c, P0, pc, z,
-                       gx, work, tb);
+                       gx, work, tb, kGradSingRatio);
     prof_end(stream, label);
     hipLaunchKernelGGL(k_grad_red1, dim3((S.M + 255) / 256, kRedT), dim3(256), 0, stream, work,
                        pc, S.M, kRedT, part);

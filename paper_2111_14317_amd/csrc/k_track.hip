@@ -10,6 +10,8 @@
 //
 // Step control (the paper fixes none; Sec. 8 only times a fixed Euler + Newton protocol):
 //   polish   : Newton at the start point until ||dN|| <= tol_polish (max_polish iterations);
+//   predicted point: rejected when its first ||dN|| exceeds tol_predict (it may lie nearer another
+//              path than its own, where the corrector would converge to the wrong path);
 //   corrector: converged when ||dN|| <= tol_track: the evaluated point is accepted, and the
 //              step doubles (up to ds_max) when it took at most one correction;
 //              otherwise apply dN while k < max_newton and ||dN|| contracts by 1/2, else reject;
@@ -54,10 +56,6 @@ constexpr int kMixedFp64Rejects = 10;
 constexpr double kMixedMinStep = 1e-6;
 // statuses of paths parked by the FP32 launch of a mixed call (internal: the call's FP64 launch
 // claims them, so they are never returned)
-// A helper launch waits at most this long (ticks of the 100 MHz constant clock) without a sign
-// of the FP32 launch's progress (a new park-list entry, a finished wave) before it stops
-// claiming; whatever it leaves is taken by the FP64 launch that follows both.
-constexpr unsigned long long kHelperPatience = 20000000ull;  // 0.2 s
 constexpr int kParked = 3;     // re-tracked in FP64 from its last accepted point
 constexpr int kParkedEnd = 4;  // at s = 0: only its endgame is left
 
@@ -95,7 +93,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
                                             int32_t *__restrict__ counters, const TrackDev &pr,
                                             unsigned long long *queue,
                                             unsigned long long *__restrict__ units,
-                                            const double *kcoef) {
+                                            const double *kcoef,
+                                            const F32Tables<N> *ft = nullptr) {
   // The side launch's re-tracks are the mixed form's critical path once the FP32 launch drains:
   // its waves take issue priority over the FP32 launch's waves on the SIMDs they share.
   if (pr.helper) __builtin_amdgcn_s_setprio(2);
@@ -166,12 +165,12 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
               if ((unsigned long long)pend >= tail) done = 1;
               else v = __hip_atomic_load(&pr.plist[pend], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (v < 0 && !done) {  // give up after kHelperPatience without any change seen
+            if (v < 0 && !done) {  // give up after pr.patience without any change seen
               const unsigned long long now = wall_clock64(), mark = (fin32 << 32) ^ tail;
               if (mark != seen) {
                 seen = mark;
                 seen_at = now;
-              } else if (now - seen_at > kHelperPatience) {
+              } else if (now - seen_at > pr.patience) {
                 done = 1;
               }
             }
@@ -245,7 +244,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           double Ml = Min;
           double zr[N], zi[N];
           load_point_lds<N, !MIXED>(sZc, n, zr, zi);
-          shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact);
+          shift_ok = eval_row<N, float>(S, r, zr, zi, sc, row, M, absum, Ml, need_exact, ft);
           const float h2 = (row[N + 1].x * row[N + 1].x + row[N + 1].y * row[N + 1].y) * fast_rcp(absum * absum);
           sing = lu_solve2<N, float>(row, r, geo.base, n, ef, qf, nE, nN, rf);
           resid = group_max_nonneg<N>(h2, r, geo.base);
@@ -354,6 +353,8 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           fin = true;
           fst = -5;
         }
+      } else if (phase == PH_TRACK && k == 0 && nrm > pr.tol_predict) {
+        act = ACT_REJECT;  // the predicted point lies outside the corrector's trust region
       } else if (phase == PH_RESUME || (phase == PH_TRACK && nrm <= pr.tol_track)) {
         if (phase == PH_TRACK) {
           ++c0;
@@ -510,8 +511,16 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
   stage_coefficients(kcoef);
   if constexpr (GT) __syncthreads();  // (staged tables end with a barrier of their own)
   const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
-  track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n, z,
-                        s, ds_io, status, counters, pr, queue, units, kcoef);
+  if constexpr (MIXED && !GT) {  // the FP32 evaluation's own tables follow the FP64 ones
+    const F32Tables<N> ft = stage_f32_tables<N>(smem + table_bytes, S);
+    track_slots<N, MIXED>(S, sd.n,
+                          reinterpret_cast<Cx<double> *>(smem + table_bytes +
+                                                         lds_f32_bytes<N>(sd.n, sd.mmax)),
+                          0, P, sd.n, z, s, ds_io, status, counters, pr, queue, units, kcoef, &ft);
+  } else {
+    track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n,
+                          z, s, ds_io, status, counters, pr, queue, units, kcoef);
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
@@ -522,7 +531,8 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
                           const TrackDev &pr, bool mixed, unsigned long long *queue,
                           hipStream_t stream, int blocks_req, int64_t *waves_out) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
-  const size_t lds = tb + track_state_bytes<N>();
+  const size_t f32 = (mixed && !S.global_tables) ? lds_f32_bytes<N>(S.n, S.mmax) : 0;
+  const size_t lds = tb + f32 + track_state_bytes<N>();
   auto kern = mixed ? (S.global_tables ? k_track<N, true, true> : k_track<N, true, false>)
                     : (S.global_tables ? k_track<N, false, true> : k_track<N, false, false>);
   int per_cu = 0;
@@ -537,7 +547,15 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
   if (waves_out) *waves_out = blocks * (kTrackBlock / 64);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, queue);
   char label[64];
-  snprintf(label, sizeof label, "k_track<%d,%s>", N, mixed ? "mixed" : (pr.helper ? "fp64-beside" : "fp64"));
+  // the plain FP64 form's launch is "fp64"; the mixed form's FP64 launches are named for their part
+  const char *part = mixed ? "mixed"
+                     : pr.helper ? "fp64-beside"
+                     : pr.polish_only ? "fp64-polish"
+                     : pr.drained_exit ? "fp64-left"
+                     : pr.claim == 8 ? "fp64-endgame"
+                     : pr.claim == (4 | 8) ? "fp64-finish"
+                     : "fp64";
+  snprintf(label, sizeof label, "k_track<%d,%s>", N, part);
   prof_begin(stream);
   unsigned long long *units = prof_units(stream);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kTrackBlock), lds, stream, S.dev(cws), c,

@@ -37,7 +37,7 @@ def cond_inf(sys, c, z, s):
 def torch_params(hom, p_oracle, precision):
     """library params with the oracle's constants"""
     kw = {f: getattr(p_oracle, f) for f in ("ds0", "ds_max", "ds_min", "tol_polish", "tol_track",
-                                            "tol_end", "res_tol", "div_re", "sing_ratio", "max_polish",
+                                            "tol_end", "res_tol", "div_re", "sing_ratio", "tol_predict", "max_polish",
                                             "max_newton", "max_end", "max_steps", "max_iters")}
     return hom.default_params(precision, **kw)
 
@@ -47,3 +47,133 @@ def mod2pi_dist(a, b):
     dre = np.abs(a.real - b.real)
     dim = np.abs(np.angle(np.exp(1j * (a.imag - b.imag))))
     return np.maximum(dre, dim).max(axis=-1)
+
+
+def _projection(z, seed=20211129):
+    """A fixed random positive combination of Re z_j, cos Im z_j and sin Im z_j per point, and the
+    sum of its weights W: two points within d of each other (max modulus, modulo 2 pi i) project
+    to within W d, since cos and sin are 1-Lipschitz."""
+    rng = np.random.default_rng(seed)
+    n = z.shape[1]
+    wr, wc, ws = (rng.uniform(0.5, 1.0, n) for _ in range(3))
+    return z.real @ wr + np.cos(z.imag) @ wc + np.sin(z.imag) @ ws, wr.sum() + wc.sum() + ws.sum()
+
+
+def _window_pairs(pa, pb_sorted, radius):
+    """For each value of pa, the index range [lo, hi) of pb_sorted within radius."""
+    lo = np.searchsorted(pb_sorted, pa - radius, side="left")
+    hi = np.searchsorted(pb_sorted, pa + radius, side="right")
+    return lo, hi
+
+
+def nearest_mod2pi(a, b, radius=1e-6):
+    """For each row of a: the smallest mod2pi_dist to a row of b among the rows within `radius`
+    (inf when there is none) and that row's index (-1).  Candidates come from a 1-D projection
+    (sorted, windowed), then the exact distance is taken."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    d_out = np.full(len(a), np.inf)
+    j_out = np.full(len(a), -1, np.int64)
+    if len(a) == 0 or len(b) == 0:
+        return d_out, j_out
+    pa, W = _projection(a)
+    pb, _ = _projection(b)
+    order = np.argsort(pb)
+    pbs = pb[order]
+    lo, hi = _window_pairs(pa, pbs, radius * W)
+    width = hi - lo
+    for k in range(int(width.max(initial=0))):
+        has = width > k
+        idx = np.nonzero(has)[0]
+        cand = order[lo[idx] + k]
+        d = mod2pi_dist(a[idx], b[cand])
+        better = d < d_out[idx]
+        d_out[idx[better]] = d[better]
+        j_out[idx[better]] = cand[better]
+    return d_out, j_out
+
+
+def distinct_count(z, tol=1e-8):
+    """number of endpoints that are pairwise more than tol apart modulo 2 pi i (a point is a
+    duplicate when an earlier point lies within tol)"""
+    z = np.asarray(z)
+    if len(z) == 0:
+        return 0
+    p, W = _projection(z)
+    order = np.argsort(p)
+    ps = p[order]
+    dup = np.zeros(len(z), bool)
+    k = 1
+    while True:
+        near = ps[k:] - ps[:-k] <= tol * W if k < len(ps) else np.zeros(0, bool)
+        if not near.any():
+            break
+        i, j = order[:-k][near], order[k:][near]
+        close = mod2pi_dist(z[i], z[j]) <= tol
+        later = np.maximum(i, j)[close]
+        dup[later] = True
+        k += 1
+    return int((~dup).sum())
+
+
+def status_hist(st):
+    u, c = np.unique(np.asarray(st), return_counts=True)
+    return {int(a): int(b) for a, b in zip(u, c)}
+
+
+def _kappa_end(sys_, z):
+    """condition number of J_z at endpoints (t = 1), from the oracle's evaluation"""
+    G, _ = oracle.eval(sys_, sys_.c, z, np.zeros(len(z)))
+    return np.abs(np.linalg.cond(G[:, :, :sys_.n], p=np.inf))
+
+
+def check_fp64_per_path(sys_, zg, sg, zo, so, label, max_excluded=0.0):
+    """FP64 tracker against the oracle's tracker, path by path: the same status on every path, and
+    endpoints within 1e-12 (max modulus, modulo 2 pi i) on every path that ends OK with a
+    well-conditioned endpoint (kappa <= 1e4; the excluded count is asserted small)."""
+    assert np.array_equal(sg, so), (label, status_hist(sg), status_hist(so))
+    ok = sg == 0
+    kap = _kappa_end(sys_, zo)
+    keep = ok & (kap <= 1e4)
+    d = mod2pi_dist(zg, zo)
+    say(f"  {label}: statuses {status_hist(sg)}, kappa > 1e4 at {int((ok & ~keep).sum())} OK endpoints, "
+        f"max d {d[keep].max() if keep.any() else 0:.2e}")
+    assert (ok & ~keep).sum() <= max_excluded * len(sg)
+    assert d[keep].max(initial=0.0) <= 1e-12
+    return d
+
+
+def check_mixed_set(sys_, zg, sg, zo, so, label, min_ok=0.999, max_swaps=0.0):
+    """Mixed tracker against the oracle's FP64 tracker: at least `min_ok` of the paths end OK,
+    every OK endpoint is a root (residual <= 1e-10), the OK endpoints are pairwise distinct, and
+    each lies within 1e-10 (modulo 2 pi i) of an OK oracle endpoint with kappa <= 1e4 (endpoints
+    are compared as sets: a path that ends on another path's root is counted as a swap).  Returns
+    the number of swaps."""
+    ok = sg == 0
+    say(f"  {label}: statuses {status_hist(sg)} (oracle {status_hist(so)})")
+    assert ok.mean() >= min_ok, status_hist(sg)
+    assert oracle.residual(sys_, sys_.c, zg[ok]).max(initial=0.0) <= 1e-10
+    zgo = zg[ok]
+    assert distinct_count(zgo) == len(zgo)
+    ref_ok = so == 0
+    kap = _kappa_end(sys_, zo[ref_ok])
+    d, j = nearest_mod2pi(zgo, zo[ref_ok])
+    assert (j >= 0).all(), "an OK endpoint with no oracle endpoint near it"
+    well = kap[j] <= 1e4
+    say(f"    set match: max d {d[well].max() if well.any() else 0:.2e} over {int(well.sum())} "
+        f"(kappa > 1e4: {int((~well).sum())})")
+    assert (~well).sum() <= 1e-3 * len(sg) + 1
+    assert d[well].max(initial=0.0) <= 1e-10
+    swaps = int((mod2pi_dist(zgo, zo[ok]) > 1e-10).sum())
+    say(f"    paths ending on another path's root: {swaps}")
+    assert swaps <= max_swaps * len(sg)
+    return swaps
+
+
+def dir_bound(kappa, n, unit_roundoff, floor):
+    """Forward-error bound of directions from one LU with partial pivoting at every point:
+    max(floor, 16 n u kappa), the backward error of the elimination (n u times a growth factor)
+    together with the evaluation's rounding, amplified by the condition number (16 covers the
+    growth factor and the evaluation)."""
+    return np.maximum(floor, 16.0 * n * unit_roundoff * np.abs(np.asarray(kappa)))
+

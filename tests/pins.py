@@ -93,6 +93,39 @@ def np_newton(sys, c, x0, iters=30, tol=1e-15):
     return x
 
 
+def np_F_J_batch(sys, c, X):
+    """F and J_x at many points X [P][n] at once (numpy, from the definition): F [P][n],
+    J [P][n][n]."""
+    A = sys.A.astype(np.float64)
+    mono = np.exp(np.log(X) @ A.T)  # x^a = e^{<a, log x>} for integer a (any branch of log)
+    terms = mono * np.asarray(c)[None, :]
+    eq = np.repeat(np.arange(sys.n), np.asarray(sys.m))
+    P, n = X.shape
+    F = np.zeros((P, n), np.complex128)
+    J = np.zeros((P, n, n), np.complex128)
+    for k in range(n):
+        sel = eq == k
+        F[:, k] = terms[:, sel].sum(1)
+        J[:, k, :] = (terms[:, sel, None] * A[None, sel, :]).sum(1) / X
+    return F, J
+
+
+def np_newton_batch(sys, c, X0, iters=30):
+    """Newton on F(x) = H(x, t=1) from every row of X0 [P][n] (numpy, affine x), until the
+    largest relative step stops shrinking (rounding level) or `iters` iterations."""
+    X = np.array(X0, np.complex128)
+    prev = np.inf
+    for _ in range(iters):
+        F, J = np_F_J_batch(sys, c, X)
+        dX = np.linalg.solve(J, -F[:, :, None])[:, :, 0]
+        X = X + dX
+        rel = (np.abs(dX).max(1) / np.abs(X).max(1)).max()
+        if rel <= 1e-15 or rel >= 0.5 * prev:
+            break
+        prev = rel
+    return X
+
+
 def mixed_volume(sys):
     n = sys.n
     supports = [sys.A[sys.equation(k)].astype(np.float64) for k in range(n)]

@@ -4,7 +4,8 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import mod2pi_dist, say
+from gpu_util import (check_fp64_per_path, check_mixed_set, distinct_count, mod2pi_dist, say,
+                      status_hist)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,10 +66,12 @@ def test_batch_equals_single_system_runs(hom, prec):
         if prec == "fp64":
             assert np.array_equal(_np(ref.z), got)
         ze, _, _, ost, _ = oracle.track(sy, sy.c, z0, -32.0)
-        ok = (ost == 0) & (sb[row:row + P] == 0)
-        assert ok.mean() >= 0.9, (q, ok.mean())
-        assert np.quantile(mod2pi_dist(got[ok], ze[ok]), 0.95) <= 1e-10
-        assert oracle.residual(sy, sy.c, got[sb[row:row + P] == 0]).max() <= 1e-10
+        if prec == "fp64":  # path by path: same statuses, <= 1e-12 where kappa <= 1e4
+            check_fp64_per_path(sy, got, sb[row:row + P], ze, ost, f"system {q}",
+                                max_excluded=0.05)
+        else:  # as a set, at most one path of the system not OK
+            check_mixed_set(sy, got, sb[row:row + P], ze, ost, f"system {q}",
+                            min_ok=(P - 1) / P, max_swaps=0.0)
         row += P
 
 
@@ -164,3 +167,56 @@ def test_batch_graph_replay(hom):
         other = hom.track(b, ct, z0, -32.0, params, sys_idx=it)  # eager work between replays
         torch.cuda.synchronize()
         assert np.array_equal(_np(other.z), ez)
+
+
+def test_c4_full_size(hom):
+    """The batched workload at full size: 256 planted-cell systems (n in 6..24, 8..64 monomials
+    per equation), 584615 paths in one launch per form.  Each form ends >= 99.9% of the paths
+    OK; every OK endpoint is a root (residual <= 1e-10) and distinct within its system.  A seeded
+    sample (2 paths of each of 64 systems) against the oracle's tracker: FP64 path by path (same
+    status, <= 1e-12 where kappa <= 1e4), the mixed form within 1e-10 unless the path ended on
+    another path's root (counted)."""
+    import concurrent.futures as cf
+    import torch
+    say("[batch c4 full] 256 systems, mixed + fp64")
+    sy = W.c4_systems()
+    systems, starts = [s_ for s_, _, _ in sy], [z0 for _, _, z0 in sy]
+    z, idx, c = W.stack_batch(systems, starts)
+    b = hom.Batch(systems)
+    ct = torch.tensor(c, dtype=torch.complex128, device="cuda")
+    it = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    zt = torch.tensor(z, dtype=torch.complex128, device="cuda")
+    rows = np.concatenate([[0], np.cumsum([len(z0) for z0 in starts])])
+    res = {}
+    for name, prec in (("mixed", hom.MIXED), ("fp64", hom.FP64)):
+        st = hom.track(b, ct, zt, -32.0, hom.default_params(prec), sys_idx=it)
+        zg, sg = _np(st.z), _np(st.status)
+        say(f"  {name}: {len(sg)} paths, statuses {status_hist(sg)}")
+        assert (sg == 0).mean() >= 0.999
+        for q, s_ in enumerate(systems):
+            zq, ok = zg[rows[q]:rows[q + 1], :s_.n], sg[rows[q]:rows[q + 1]] == 0
+            assert oracle.residual(s_, s_.c, zq[ok]).max(initial=0.0) <= 1e-10, (name, q)
+            assert distinct_count(zq[ok]) == int(ok.sum()), (name, q)
+        res[name] = (zg, sg)
+    rng = np.random.default_rng(404)
+    picks = [(int(q), rng.choice(len(starts[q]), 2, replace=False)) for q in
+             rng.choice(len(systems), 64, replace=False)]
+
+    def ora(item):
+        q, loc = item
+        ze, _, _, ost, _ = oracle.track(systems[q], systems[q].c, starts[q][loc], -32.0, threads=1)
+        return ze, ost
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(ora, picks))
+    swaps = 0
+    for (q, loc), (ze, ost) in zip(picks, refs):
+        s_ = systems[q]
+        zf, sf = res["fp64"][0][rows[q] + loc, :s_.n], res["fp64"][1][rows[q] + loc]
+        check_fp64_per_path(s_, zf, sf, ze, ost, f"system {q}", max_excluded=0.5)
+        zm, sm = res["mixed"][0][rows[q] + loc, :s_.n], res["mixed"][1][rows[q] + loc]
+        d = mod2pi_dist(zm, ze)
+        both = (sm == 0) & (ost == 0)
+        swaps += int((both & (d > 1e-10)).sum())  # roots and distinct: checked above
+    say(f"  sampled mixed paths ending on another path's root: {swaps} of {2 * len(picks)}")
+    assert swaps == 0

@@ -5,7 +5,8 @@ import pytest
 import oracle
 import pins
 import workloads as W
-from gpu_util import mod2pi_dist, say, torch_params
+from gpu_util import (check_fp64_per_path, check_mixed_set, mod2pi_dist, say, status_hist,
+                      torch_params)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,52 +49,43 @@ def test_c1_all_mixed_volume_paths(hom, prec):
 
 
 def test_fp64_matches_oracle_per_path(hom):
-    """n=8 planted-cell paths: same status and same endpoint per path; counters close."""
+    """n=8 planted-cell paths: the same status and the same endpoint on every path; counters
+    close."""
     say("[track c5 fp64 per-path] P=512")
     csys, cell, z0 = W.planted_config("c5", P=512)
     p = oracle.TrackParams()
     h = hom.System.from_workload(csys)
     st = hom.track(h, csys.c, z0, -32.0, torch_params(hom, p, hom.FP64))
     ze, se, _, ost, ocnt = oracle.track(csys, csys.c, z0, -32.0, p)
-    gst = _np(st.status)
-    both = (gst == 0) & (ost == 0)
-    say(f"  ok gpu {np.mean(gst == 0):.4f} oracle {np.mean(ost == 0):.4f}")
-    assert both.mean() >= 0.99
-    d = mod2pi_dist(_np(st.z)[both], ze[both])
-    assert np.quantile(d, 0.99) <= 1e-12
+    check_fp64_per_path(csys, _np(st.z), _np(st.status), ze, ost, "fp64")
     gc = _np(st.counters)
     assert abs(gc[:, 3].mean() / ocnt[:, 3].mean() - 1) < 0.02
-    assert oracle.residual(csys, csys.c, _np(st.z)[gst == 0]).max() <= 1e-10
+    assert oracle.residual(csys, csys.c, _np(st.z)[_np(st.status) == 0]).max() <= 1e-10
 
 
-def test_mixed_matches_fp64_endpoints(hom):
+def test_mixed_matches_oracle_endpoints(hom):
     say("[track c5 mixed] P=512")
     csys, cell, z0 = W.planted_config("c5", P=512)
     h = hom.System.from_workload(csys)
-    a = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64))
     b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
-    sa, sb = _np(a.status), _np(b.status)
-    assert (sb == 0).mean() >= 0.99
-    both = (sa == 0) & (sb == 0)
-    d = mod2pi_dist(_np(a.z)[both], _np(b.z)[both])
-    assert np.quantile(d, 0.99) <= 1e-10
-    assert oracle.residual(csys, csys.c, _np(b.z)[sb == 0]).max() <= 1e-10
+    ze, _, _, ost, _ = oracle.track(csys, csys.c, z0, -32.0)
+    check_mixed_set(csys, _np(b.z), _np(b.status), ze, ost, "mixed", max_swaps=0.0)
 
 
-def test_c2_subset_distinct_roots(hom):
-    """n=10: 4096 planted-cell paths in both forms; >= 99.9% OK, distinct endpoints, residuals."""
-    say("[track c2 subset] P=4096")
-    csys, cell, z0 = W.planted_config("c2", P=4096)
+def test_c2_full_endpoint_parity(hom):
+    """The n = 10 workload at full size, 65536 planted-cell paths, against the oracle's tracker:
+    FP64 path by path (same status everywhere, <= 1e-12 on every well-conditioned endpoint); the
+    mixed form as a set (>= 99.9% OK, every OK endpoint distinct, a root, and within 1e-10 of an
+    oracle endpoint), with its failures reported by status."""
+    say("[track c2 full] P=65536 fp64 + mixed vs oracle")
+    csys, cell, z0 = W.planted_config("c2", P=65536)
     h = hom.System.from_workload(csys)
-    for prec in (hom.FP64, hom.MIXED):
-        st = hom.track(h, csys.c, z0, -32.0, hom.default_params(prec))
-        s = _np(st.status)
-        ok = s == 0
-        say(f"  prec {prec}: ok {ok.mean():.5f} evals/path {_np(st.counters)[:, 3].mean():.1f}")
-        assert ok.mean() >= 0.999
-        z = _np(st.z)[ok]
-        assert len(_key(z)) == len(z)
-        assert oracle.residual(csys, csys.c, z).max() <= 1e-10
+    ze, _, _, ost, _ = oracle.track(csys, csys.c, z0, -32.0)
+    say(f"  oracle: {status_hist(ost)}")
+    a = hom.track(h, csys.c, z0, -32.0, torch_params(hom, oracle.TrackParams(), hom.FP64))
+    check_fp64_per_path(csys, _np(a.z), _np(a.status), ze, ost, "fp64", max_excluded=1e-3)
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
+    check_mixed_set(csys, _np(b.z), _np(b.status), ze, ost, "mixed", max_swaps=0.0)
 
 
 def test_resume_bitwise(hom):
@@ -132,6 +124,19 @@ def test_mixed_beside_equals_serial(hom):
     assert (_np(a.status) == 0).mean() >= 0.999
 
 
+def test_mixed_side_nowait_equals_serial(hom):
+    """The side launch's hand-over: with TRACK_SIDE_NOWAIT it gives up as soon as it finds no
+    parked path waiting, and the call's last launch re-tracks what it left; the results still
+    equal the serial order bit for bit."""
+    say("[track mixed side nowait vs serial] c2 P=16384")
+    csys, cell, z0 = W.planted_config("c2", P=16384)
+    h = hom.System.from_workload(csys)
+    a = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED, flags=hom.TRACK_SIDE_NOWAIT))
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED, flags=hom.TRACK_SERIAL))
+    for f in ("z", "s", "ds", "status", "counters"):
+        assert np.array_equal(_np(getattr(a, f)), _np(getattr(b, f))), f
+
+
 def test_deterministic_and_batch_independent(hom):
     """Bitwise-equal endpoints across runs and when the path set is split."""
     say("[track determinism] c5 P=300")
@@ -166,22 +171,16 @@ def test_failure_modes_forced(hom):
 @pytest.mark.parametrize("n", [2, 4, 6, 7, 12, 13, 16, 20, 24, 32])
 def test_every_group_size(hom, n):
     """One planted system per compiled group size (n = 13 and 16 both run on 16-lane groups;
-    n = 24, 32 read their tables from global memory): both precisions end >= 95% of the paths
-    OK, FP64 endpoints match the oracle's, every OK endpoint is a root."""
+    n = 24, 32 read their tables from global memory), 40 paths: FP64 matches the oracle path by
+    path, the mixed form matches it as a set."""
     say(f"[track group size] n={n} P=40")
     rng = np.random.default_rng(200 + n)
     sy = W.random_system(n, 10, W._uniform_exps(-3, 3), "unit", 63, rng, rng, rng)
     csys, cell = W.plant_cell(sy, 63, rng, min_det=40)
     z0 = W.binomial_start_points(csys, cell, 40, rng)
     h = hom.System.from_workload(csys)
-    ze, _, _, ost, _ = oracle.track(csys, csys.c, z0[:16], -32.0)
-    for prec in (hom.FP64, hom.MIXED):
-        st = hom.track(h, csys.c, z0, -32.0, hom.default_params(prec))
-        s = _np(st.status)
-        say(f"  prec {prec}: ok {(s == 0).mean():.3f}")
-        assert (s == 0).mean() >= 0.95, np.unique(s, return_counts=True)
-        ok = s == 0
-        assert oracle.residual(csys, csys.c, _np(st.z)[ok]).max() <= 1e-10
-        both = ok[:16] & (ost == 0)
-        tol = 1e-12 if prec == hom.FP64 else 1e-10
-        assert np.quantile(mod2pi_dist(_np(st.z)[:16][both], ze[both]), 0.9) <= tol
+    ze, _, _, ost, _ = oracle.track(csys, csys.c, z0, -32.0)
+    a = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.FP64))
+    check_fp64_per_path(csys, _np(a.z), _np(a.status), ze, ost, "fp64")
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
+    check_mixed_set(csys, _np(b.z), _np(b.status), ze, ost, "mixed", min_ok=1.0)

@@ -171,6 +171,21 @@ def c4_systems(num_sys=256, P_lo=512, P_hi=4096, W=63, min_det=None):
     return out
 
 
+def stack_batch(systems, starts):
+    """The arrays of a batched call: start points zero padded to the largest n (z [P][n_max]),
+    each path's system index (non-decreasing) and the concatenated coefficients."""
+    n_max = max(s.n for s in systems)
+    P = sum(len(z0) for z0 in starts)
+    z = np.zeros((P, n_max), np.complex128)
+    idx = np.concatenate([np.full(len(z0), q, np.int32) for q, z0 in enumerate(starts)])
+    row = 0
+    for z0 in starts:
+        z[row:row + len(z0), :z0.shape[1]] = z0
+        row += len(z0)
+    c = np.concatenate([s.c for s in systems])
+    return z, idx, c
+
+
 # --------------------------------------------------------------------------------------------
 # integer Smith normal form  U D V = diag(sigma), U, V unimodular
 # --------------------------------------------------------------------------------------------
