@@ -221,6 +221,24 @@ int hom_track(hom_system_t sys, const double *c, int64_t P, double *z, double *s
               int32_t *counters, hom_stream_t stream);
 
 /*
+ * hom_track without any device allocation, for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, rules
+ * and results as hom_track on a single-system handle (the mixed form's three launches run in
+ * their serial order, as with HOM_TRACK_SERIAL, so the results equal hom_track's bit for bit).
+ * Its work-queue counters and, for a system whose tables stay in global memory, this call's
+ * coefficient table live in one static device array of HOM_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; the kernels clear what must start at zero.  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (other streams, other threads) race
+ * and must not be made.  No profiling records are made for it.
+ * Errors: as hom_track; HOM_EUNSUPPORTED for batch handles and for systems whose coefficient
+ * table (24 bytes per entry of the largest m_k x n table) exceeds the scratch.
+ */
+#define HOM_NOALLOC_SCRATCH_BYTES (4u << 20) /* 4 MiB per GPU */
+int hom_track_noalloc(hom_system_t sys, const double *c, int64_t P, double *z, double *s,
+                      double *ds, const hom_track_params *params, int32_t *status,
+                      int32_t *counters, hom_stream_t stream);
+
+/*
  * Gradient of a real loss L(x*) on endpoints x* = e^{z_end} (t = 1) with respect to the
  * coefficients, by the implicit function theorem (the argument behind the Davidenko equation,
  * Sec. 2.3).  Per path: J_x^H nu = -g, computed as J_z^H nu = -conj(x*) .* g; then

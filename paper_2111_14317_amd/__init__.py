@@ -32,8 +32,8 @@ PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
 TRACK_EXACT_SHIFT, TRACK_SERIAL, TRACK_SIDE_NOWAIT = 1, 2, 4
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
-            "hom_track_params_default", "hom_track", "hom_endpoint_grad", "hom_set_profiling",
-            "hom_profile_read", "hom_last_error"]
+            "hom_track_params_default", "hom_track", "hom_track_noalloc", "hom_endpoint_grad",
+            "hom_set_profiling", "hom_profile_read", "hom_last_error"]
 
 
 class HomError(RuntimeError):
@@ -72,6 +72,7 @@ def _load():
     lib.hom_step.argtypes = [P, P, i64, P, P, P, P, P, i32, P]
     lib.hom_track_params_default.argtypes = [ctypes.POINTER(TrackParams), i32]
     lib.hom_track.argtypes = [P, P, i64, P, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
+    lib.hom_track_noalloc.argtypes = [P, P, i64, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
     lib.hom_endpoint_grad.argtypes = [P, P, i64, P, P, P, i32, P]
     lib.hom_set_profiling.argtypes = [i32]
     lib.hom_profile_read.argtypes = [P, P, P, i32]
@@ -241,6 +242,30 @@ def track(sys: System, c, z0, s0, params: TrackParams | None = None, state: Trac
                          _ptr(sys_idx), ctypes.byref(params), _ptr(state.status),
                          _ptr(state.counters), _stream()))
     return state
+
+
+def track_noalloc(sys: System, c, state: TrackState, params: TrackParams | None = None):
+    """hom_track_noalloc on an existing state (z, s, ds, status, counters, updated in place): the
+    tracker with the library's static device scratch instead of any allocation (single-system
+    handles; the mixed form's launches in serial order)."""
+    params = params or default_params()
+    P = state.z.shape[0]
+    _check(lib.hom_track_noalloc(sys.handle, _ptr(c), P, _ptr(state.z), _ptr(state.s),
+                                 _ptr(state.ds), ctypes.byref(params), _ptr(state.status),
+                                 _ptr(state.counters), _stream()))
+    return state
+
+
+def new_state(z0, s0, device="cuda") -> TrackState:
+    """A fresh tracking state: start points z0 [P][n] at s0, every path HOM_PATH_START."""
+    import torch
+    z = torch.as_tensor(np.asarray(z0), dtype=torch.complex128, device=device).contiguous().clone()
+    P = z.shape[0]
+    s = torch.empty(P, dtype=torch.float64, device=device)
+    s.copy_(_dev_like(s0, torch.float64, device).reshape(-1).expand(P))
+    return TrackState(z, s, torch.zeros(P, dtype=torch.float64, device=device),
+                      torch.full((P,), PATH_START, dtype=torch.int32, device=device),
+                      torch.zeros((P, 4), dtype=torch.int32, device=device))
 
 
 def endpoint_grad(sys: System, c, z_end, grad_x, precision=FP64, device="cuda"):

@@ -758,6 +758,81 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   return HOM_OK;
 }
 
+// ---- hom_track_noalloc: the tracker with the library's static device scratch ----
+// The scratch array lives in this file.  Its name is a host-side stand-in in host code: kernels
+// and copies get the device address that hipGetSymbolAddress returns, resolved once per device
+// (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[HOM_NOALLOC_SCRATCH_BYTES];
+static constexpr size_t kScratchCounters = 256;  // work-queue counters, then the coefficients
+
+static hipError_t scratch_ptr(unsigned char **out) {
+  static std::mutex mu;
+  static unsigned char *ptrs[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptrs[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
+
+int hom_track_noalloc(hom_system_t h, const double *c, int64_t P, double *z, double *s, double *ds,
+                      const hom_track_params *params, int32_t *status, int32_t *counters,
+                      hom_stream_t stream) {
+  g_err.clear();
+  if (h && h->s.num_sys > 0)
+    HOM_FAIL(HOM_EUNSUPPORTED, "hom_track_noalloc: batch handles are not supported (hom_track)");
+  bool none = false;
+  const int rc = check_track_args("hom_track_noalloc", h, c, P, z, s, ds, nullptr, params, status,
+                                  counters, &none);
+  if (rc != HOM_OK || none) return rc;
+  const size_t need = kScratchCounters + h->s.coeff_ws_bytes();
+  if (need > (size_t)HOM_NOALLOC_SCRATCH_BYTES)
+    HOM_FAIL(HOM_EUNSUPPORTED,
+             "hom_track_noalloc: the system's coefficient table (" +
+                 std::to_string(h->s.coeff_ws_bytes()) + " bytes) exceeds the static scratch of " +
+                 std::to_string((size_t)HOM_NOALLOC_SCRATCH_BYTES - kScratchCounters) +
+                 " bytes; use hom_track");
+  unsigned char *base = nullptr;
+  HOM_HIP(scratch_ptr(&base), "hom_track_noalloc: scratch address");
+  hipStream_t st = (hipStream_t)stream;
+  // no profiling records here: they would create events
+  const bool prof = g_prof;
+  g_prof = false;
+  unsigned long long *queue = reinterpret_cast<unsigned long long *>(base);
+  void *cws = h->s.global_tables ? static_cast<void *>(base + kScratchCounters) : nullptr;
+  const TrackDev pr = to_dev(params);
+  hipError_t e = hipSuccess;
+  if (cws) e = launch_coeff_tables(h->s, c, cws, st);
+  if (params->precision == HOM_FP64) {
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr, false, queue, st);
+  } else {  // the three launches of the mixed form in their serial order (no second stream)
+    TrackDev pr_pol = pr, pr32 = pr, pr64 = pr;
+    pr_pol.claim = 1;
+    pr_pol.polish_only = 1;
+    pr32.claim = 2;
+    pr64.claim = 4 | 8;
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr_pol, false, queue, st);
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr32, true, queue, st);
+    if (e == hipSuccess)
+      e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
+  }
+  g_prof = prof;
+  HOM_HIP(e, "hom_track_noalloc");
+  return HOM_OK;
+}
+
 int hom_endpoint_grad(hom_system_t h, const double *c, int64_t P, const double *z_end,
                       const double *grad_x, double *grad_c, int precision, hom_stream_t stream) {
   g_err.clear();
