@@ -12,6 +12,9 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   step            pinned: LAPACK solve, Cramer's rule, closed-form directions of binomial systems
   track           pinned: closed-form binomial paths, mixed-volume root count, residuals
   endpoint_grad   pinned: central finite differences of re-solved endpoints
+  step_proj       pinned: homogeneity of degree one under y -> lambda y, the affine directions
+                  mapped into homogeneous coordinates (from the affine evaluation and numpy
+                  solves, through Euler's identity), exact rational Cramer solutions
   residual        pinned: hand-worked exact values (tests/golden/residual_2x2.json), exact
                   rational arithmetic at rational points, the closed form at perturbed binomial
                   roots, zeros at roots, coefficient-scale and branch invariance
@@ -59,8 +62,9 @@ def _load():
         _lib.oracle_track.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
         _lib.oracle_residual.argtypes = [i32, P, P, P, i64, P, P, i32]
         _lib.oracle_endpoint_grad.argtypes = [i32, P, P, P, P, i64, P, P, P]
+        _lib.oracle_step_proj.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
         for name in ("oracle_eval", "oracle_step", "oracle_track", "oracle_residual",
-                     "oracle_endpoint_grad"):
+                     "oracle_endpoint_grad", "oracle_step_proj"):
             getattr(_lib, name).restype = i32
     return _lib
 
@@ -123,6 +127,31 @@ def step(sys, c, z, s, threads=None):
     _checked(lib.oracle_step(n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(z), _ptr(s), _ptr(dE),
                              _ptr(dN), _ptr(st), _ptr(ratio), threads or default_threads()))
     return dE, dN, st, ratio
+
+
+def step_proj(sys, c, y, s, threads=None):
+    """Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)) at points
+    y [P][n+1] (y_j pairs with x_j for j < n; y_n is the homogenising coordinate, so an affine
+    point x is y = (x, 1)): [dH~/dy; y^*] dE = [-dH~/ds; 0] and [dH~/dy; y^*] dN = [-H~; 0].
+    Returns (dE, dN, status, ratio, d) with d [n] the homogenising degrees."""
+    lib = _load()
+    m, A, w = _sys_arrays(sys)
+    c = np.ascontiguousarray(c, np.complex128)
+    y = np.ascontiguousarray(y, np.complex128).reshape(-1, sys.n + 1)
+    s = np.ascontiguousarray(np.broadcast_to(np.asarray(s, np.float64), (y.shape[0],)))
+    P, nu = y.shape
+    dE = np.zeros((P, nu), np.complex128)
+    dN = np.zeros((P, nu), np.complex128)
+    st = np.zeros(P, np.int32)
+    ratio = np.zeros(P, np.float64)
+    d = np.zeros(sys.n, np.int32)
+    code = lib.oracle_step_proj(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(y), _ptr(s),
+                                _ptr(dE), _ptr(dN), _ptr(st), _ptr(ratio), _ptr(d),
+                                threads or default_threads())
+    if code == -2:
+        raise ValueError("oracle: a homogenising exponent exceeds 127")
+    _checked(code)
+    return dE, dN, st, ratio, d
 
 
 @dataclasses.dataclass

@@ -19,6 +19,9 @@
  *   - track: a predictor-corrector loop over s in [s0, 0] that uses dE as Euler predictor and dN
  *            as Newton corrector (Sec. 2.3); the paper gives no step control, so the constants
  *            and rules are taken from the parameter struct below.
+ *   - proj : the Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)):
+ *            the homogenised system's Jacobian with the row y^*, one (n+1) x (n+1) solve for
+ *            both (the unified system of Sec. 6, solved plainly instead of by QR).
  *   - grad : gradient of a real loss on the endpoints with respect to the coefficients, through
  *            the implicit function theorem (the same argument as the Davidenko equation,
  *            Sec. 2.3): J_x^H nu = -g, grad c_{k,a} = sum_paths nu_k conj(x^a).
@@ -38,6 +41,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <limits.h>
 
 typedef double complex cplx;
 
@@ -229,6 +233,134 @@ int oracle_step(int n, const int32_t *m, const int8_t *A, const double *w, const
         double r;
         int st = step_point(n, m, A, w, (const cplx *)c, (const cplx *)z + p * n, s[p],
                             (cplx *)dE + p * n, (cplx *)dN + p * n, &r, NULL);
+        status[p] = st ? -1 : 0;
+        if (ratio) ratio[p] = r;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* projective step                                                                            */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Homogenising exponent of monomial a of equation k (Sec. 2.2): the homogenised exponent vector
+ * is (a, d_k - sum_j a_j) with d_k = max over the monomials of equation k of sum_j a_j, so that
+ * every monomial of h~_k has total degree d_k and the extra exponent is non-negative.  d [n]. */
+static void homog_degrees(int n, const int32_t *m, const int8_t *A, int32_t *d) {
+    int off = 0;
+    for (int k = 0; k < n; k++) {
+        int dk = INT32_MIN;
+        for (int i = off; i < off + m[k]; i++) {
+            int t = 0;
+            for (int j = 0; j < n; j++) t += A[(size_t)i * n + j];
+            if (t > dk) dk = t;
+        }
+        d[k] = dk;
+        off += m[k];
+    }
+}
+
+/* One point y in C^{n+1} (homogeneous coordinates; y_j pairs with a_j for j < n and y_n with the
+ * homogenising exponent).  The homogenised homotopy (Sec. 2.2, eq. (3)) is
+ *   h~_k(y, s) = sum_a c_{k,a} y^{(a, d_k - |a|)} e^{s w_k(a)},
+ * its partials dh~_k/dy_j = sum_a e_j c y^{(a, d_k - |a|) - e_j} e^{s w} (e_j the j-th exponent),
+ * dh~_k/ds = sum_a w c y^(...) e^{s w}.  The Euler and Newton directions in homogeneous
+ * coordinates solve (eq. (4), (5); the unified system of Sec. 6)
+ *   [ dH~/dy ; y^* ] dE = [ -dH~/ds ; 0 ],     [ dH~/dy ; y^* ] dN = [ -H~ ; 0 ],
+ * an (n+1) x (n+1) system with two right-hand sides, solved here by LU with partial pivoting.
+ * Row k of the equations is scaled by e^{-M_k} (M_k = max over its monomials of
+ * <e, log|y|> + s w) so that no term over- or underflows; the solution does not depend on it.
+ * The terms are formed in polar form: phase by repeated multiplication of y_j/|y_j|, magnitude
+ * exp(<e, log|y|> + s w - M_k).  Returns 0, or 1 when a pivot is exactly zero. */
+static int step_proj_point(int n, const int32_t *m, const int8_t *A, const double *w,
+                           const cplx *c, const int32_t *d, const cplx *y, double s, cplx *dE,
+                           cplx *dN, double *ratio) {
+    const int nu = n + 1; /* unknowns */
+    cplx u[OR_NMAX + 1], uinv[OR_NMAX + 1], yinv[OR_NMAX + 1];
+    double ly[OR_NMAX + 1];
+    for (int j = 0; j < nu; j++) {
+        ly[j] = log(cabs(y[j]));
+        u[j] = y[j] / cabs(y[j]);
+        uinv[j] = conj(u[j]);
+        yinv[j] = 1.0 / y[j];
+    }
+    /* augmented (n+1) x (n+3): [dH~/dy | -dH~/ds ... ] built as [dH~/dy | dH~/ds | H~] rows
+     * for the equations and [y^* | 0 | 0] for the last row; lu_solve negates the right-hand
+     * sides. */
+    cplx G[(OR_NMAX + 1) * (OR_NMAX + 3)];
+    const int ld = nu + 2;
+    int off = 0;
+    for (int k = 0; k < n; k++) {
+        cplx *row = G + (size_t)k * ld;
+        for (int col = 0; col < ld; col++) row[col] = 0.0;
+        int8_t e[OR_NMAX + 1];
+        double Mk = -INFINITY;
+        for (int i = off; i < off + m[k]; i++) {
+            int tot = 0;
+            double lm = s * w[i];
+            for (int j = 0; j < n; j++) {
+                tot += A[(size_t)i * n + j];
+                lm += A[(size_t)i * n + j] * ly[j];
+            }
+            lm += (double)(d[k] - tot) * ly[n];
+            if (lm > Mk) Mk = lm;
+        }
+        for (int i = off; i < off + m[k]; i++) {
+            int tot = 0;
+            for (int j = 0; j < n; j++) {
+                e[j] = A[(size_t)i * n + j];
+                tot += e[j];
+            }
+            e[n] = (int8_t)(d[k] - tot);
+            double lm = s * w[i] - Mk;
+            for (int j = 0; j < nu; j++) lm += e[j] * ly[j];
+            const cplx term = c[i] * monomial(nu, u, uinv, e) * exp(lm);
+            for (int j = 0; j < nu; j++) row[j] += (double)e[j] * term * yinv[j];
+            row[nu] += w[i] * term;
+            row[nu + 1] += term;
+        }
+        off += m[k];
+    }
+    cplx *last = G + (size_t)n * ld;
+    for (int j = 0; j < nu; j++) last[j] = conj(y[j]);
+    last[nu] = 0.0;
+    last[nu + 1] = 0.0;
+    cplx X[2 * (OR_NMAX + 1)];
+    int st = lu_solve(nu, 2, G, ld, X, ratio);
+    for (int j = 0; j < nu; j++) {
+        dE[j] = st ? NAN : X[j];
+        dN[j] = st ? NAN : X[nu + j];
+    }
+    return st;
+}
+
+/* Projective Euler and Newton directions at P points y [P][n+1] (complex), s [P]; dE, dN
+ * [P][n+1]; status 0 or -1 (a zero pivot); ratio min|pivot| / max|pivot| (optional).  The
+ * homogenising degrees d [n] are written when d_out is not NULL.  The homogenising exponents must
+ * fit int8 (|d_k - |a|| <= 127); returns -1 for n out of range, -2 otherwise. */
+int oracle_step_proj(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                     int64_t P, const double *y, const double *s, double *dE, double *dN,
+                     int32_t *status, double *ratio, int32_t *d_out, int threads) {
+    if (n < 1 || n > OR_NMAX) return -1;
+    int32_t d[OR_NMAX];
+    homog_degrees(n, m, A, d);
+    int off = 0;
+    for (int k = 0; k < n; k++) {
+        for (int i = off; i < off + m[k]; i++) {
+            int tot = 0;
+            for (int j = 0; j < n; j++) tot += A[(size_t)i * n + j];
+            if (d[k] - tot > 127) return -2;
+        }
+        off += m[k];
+    }
+    if (d_out)
+        for (int k = 0; k < n; k++) d_out[k] = d[k];
+    const int nu = n + 1;
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+    for (int64_t p = 0; p < P; p++) {
+        double r;
+        int st = step_proj_point(n, m, A, w, (const cplx *)c, d, (const cplx *)y + p * nu, s[p],
+                                 (cplx *)dE + p * nu, (cplx *)dN + p * nu, &r);
         status[p] = st ? -1 : 0;
         if (ratio) ratio[p] = r;
     }
