@@ -526,6 +526,55 @@ def error_table(hom, torch, csys, mixed, fp64, ora_z, ora_st, c5):
     return out
 
 
+def flops_step_proj(n, M):
+    """Algorithmic flops of one projective step (n equations, n + 1 homogeneous unknowns, M
+    monomials): A1 over n + 1 coordinates and the lifting, A2, A3 with n + 3 columns, the
+    y-coordinate epilogue, the Householder LQ of the (n+1) x (n+3) unified system (complex: 4 real
+    flops per multiply-add) and the two null vectors."""
+    nu, cols = n + 1, n + 3
+    a1 = 2 * (2 * nu + 1) * M
+    a2 = 6 * M
+    a3 = M * (4 * (nu + 1) + 2)
+    epi = 6 * n * nu
+    lq = 4 * (2 * cols * nu * nu - 2 * nu ** 3 // 3)
+    null = 2 * 2 * 8 * sum(cols - i for i in range(nu))
+    return a1 + a2 + a3 + epi + lq + null
+
+
+def run_step_proj(hom, torch, P=65536, reps=5):
+    """hom_step_proj on P random homogeneous points of the n = 10 system: kernel ms (library
+    events), points/s and the algorithmic FP64 rate."""
+    import numpy as np
+
+    import workloads as W
+    sys_, z, s = W.config_system("c2", P=P)
+    rng = np.random.default_rng(5)
+    lam = np.exp(rng.normal(0, 0.5, P) + 1j * rng.uniform(0, 2 * np.pi, P))
+    y = np.concatenate([np.exp(z), np.ones((P, 1))], axis=1) * lam[:, None]
+    h = hom.System.from_workload(sys_, projective=True)
+    dev = "cuda"
+    c = torch.tensor(sys_.c, dtype=torch.complex128, device=dev)
+    yt = torch.tensor(y, dtype=torch.complex128, device=dev)
+    st = torch.tensor(s, dtype=torch.float64, device=dev)
+    out = hom.step_proj(h, c, yt, st)
+    torch.cuda.synchronize()
+    hom.profile_read()
+    hom.set_profiling(True)
+    for _ in range(reps):
+        out = hom.step_proj(h, c, yt, st)
+    torch.cuda.synchronize()
+    hom.set_profiling(False)
+    ms = sum(t for _, t, _ in hom.profile_read()) / reps
+    fl = flops_step_proj(sys_.n, int(np.sum(sys_.m)))
+    ok = float((out[2] == 0).float().mean())
+    rec = {"points": P, "ms": ms, "points_per_s": P / (ms * 1e-3), "flops_per_point": fl,
+           "tflops_algorithmic": P * fl / (ms * 1e-3) / 1e12,
+           "frac_of_fp64_peak": P * fl / (ms * 1e-3) / PEAK_FP64, "ok_frac": ok}
+    print(f"# step_proj n10 P={P}: {ms:.3f} ms, {rec['points_per_s']:.3e} points/s, "
+          f"{rec['tflops_algorithmic']:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    return rec
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -651,6 +700,7 @@ def main():
         out["eval_step_n10_65536_points"] = run_eval_n10(hom, torch, P=65536)
         out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)
         out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
+        out["step_proj_n10_65536_points"] = run_step_proj(hom, torch)
     if not args.no_batch:
         out["batch_c4"] = run_c4(hom, torch)
     c5 = None

@@ -59,6 +59,7 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
 
 /* hom_create flags */
 #define HOM_CREATE_VALU 1 /* build no matrix-core tables (see hom_create) */
+#define HOM_CREATE_PROJECTIVE 2 /* the homogenised system in n + 1 unknowns (hom_step_proj only) */
 
 /* per-path status (hom_step: OK or SINGULAR; hom_track: all) */
 #define HOM_PATH_OK 0            /* reached s = 0, endgame converged, residual <= res_tol */
@@ -82,7 +83,7 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
  * tile of 16 points (FP64: 16x16x4 f64 MFMA; HOM_EVAL_FP32 / HOM_MIXED: BF16x3, i.e. z and the
  * exponentials split into three bf16 parts with FP32 accumulation, the phase formed exactly
  * from integer digit sums); hom_step keeps the LU on the vector units.  flags: 0 or
- * HOM_CREATE_VALU (no matrix-core tables).
+ * HOM_CREATE_VALU (no matrix-core tables), HOM_CREATE_PROJECTIVE (a handle for hom_step_proj).
  * n in [1, 32]; m[k] >= 1; M <= 65536.  Synchronous.
  * Errors: HOM_EINVAL (bad argument), HOM_ENOMEM, HOM_EDEVICE.
  */
@@ -140,6 +141,27 @@ int hom_eval(hom_system_t sys, const double *c, int64_t P, const double *z, cons
 int hom_step(hom_system_t sys, const double *c, int64_t P, const double *z, const double *s,
              double *dz_euler, double *dz_newton, int32_t *status, int precision,
              hom_stream_t stream);
+
+/*
+ * The Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)), computed as
+ * in Sec. 6 and Alg. 2-3: from the null space of the unified system
+ *   J = [ dH~/dy  dH~/ds  H~ ; y^*  0  0 ]      ((n+1) x (n+3))
+ * by Householder reflections (the QR decomposition of J^T), then the row reduction that makes the
+ * two null vectors' last two entries the identity: (dy_euler, 1, 0) and (dy_newton, 0, 1).  So
+ *   dH~/dy dy_euler + dH~/ds = 0,  y^* dy_euler = 0;   dH~/dy dy_newton + H~ = 0,  y^* dy_newton = 0.
+ * The handle must come from hom_create with HOM_CREATE_PROJECTIVE: its equation k is homogenised
+ * as h~_k(y, s) = sum_a c_a y^(a, d_k - |a|) e^{s w(a)} with d_k the largest total degree |a| of
+ * the equation's monomials (the homogenising exponents must not exceed 127; n <= 29).  y_j pairs
+ * with x_j for j < n and y_n is the homogenising coordinate, so an affine point x is y = (x, 1).
+ * The evaluation runs in log coordinates z = log y (A1-A3) followed by the y-coordinate epilogue
+ * of Alg. 2 (column j times 1 / y_j); every y_j must be nonzero.
+ * c: complex128 [M]; y: complex128 [P][n+1]; s: double [P]; dy_euler, dy_newton: complex128
+ * [P][n+1]; status: int32 [P] (HOM_PATH_OK, or HOM_PATH_SINGULAR when min|L_jj| / max|L_jj| of
+ * the triangular factor is below 1e-14, the 2 x 2 block is singular or a result is not finite).
+ * FP64.  P = 0 is a no-op.
+ */
+int hom_step_proj(hom_system_t sys, const double *c, int64_t P, const double *y, const double *s,
+                  double *dy_euler, double *dy_newton, int32_t *status, hom_stream_t stream);
 
 /* Tracker constants.  The paper fixes no step control; these are this library's rules. */
 typedef struct {

@@ -25,15 +25,15 @@ LIB_PATH = os.path.join(_HERE, "libhom.so")
 HOM_OK, HOM_EINVAL, HOM_ENOMEM, HOM_EDEVICE, HOM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
 UNSCALED, AFFINE, EVAL_FP32, EVAL_VALU = 1, 2, 4, 8
-CREATE_VALU = 1
+CREATE_VALU, CREATE_PROJECTIVE = 1, 2
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
 TRACK_EXACT_SHIFT, TRACK_SERIAL, TRACK_SIDE_NOWAIT = 1, 2, 4
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
-            "hom_track_params_default", "hom_track", "hom_track_noalloc", "hom_endpoint_grad",
-            "hom_set_profiling", "hom_profile_read", "hom_last_error"]
+            "hom_step_proj", "hom_track_params_default", "hom_track", "hom_track_noalloc",
+            "hom_endpoint_grad", "hom_set_profiling", "hom_profile_read", "hom_last_error"]
 
 
 class HomError(RuntimeError):
@@ -70,6 +70,7 @@ def _load():
     lib.hom_system_info.argtypes = [P, P, P, P, P]
     lib.hom_eval.argtypes = [P, P, i64, P, P, P, P, i32, P]
     lib.hom_step.argtypes = [P, P, i64, P, P, P, P, P, i32, P]
+    lib.hom_step_proj.argtypes = [P, P, i64, P, P, P, P, P, P]
     lib.hom_track_params_default.argtypes = [ctypes.POINTER(TrackParams), i32]
     lib.hom_track.argtypes = [P, P, i64, P, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
     lib.hom_track_noalloc.argtypes = [P, P, i64, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
@@ -117,21 +118,23 @@ class System:
 
     num_sys = 1
 
-    def __init__(self, n, m, A, w, valu=False):
+    def __init__(self, n, m, A, w, valu=False, projective=False):
         m = np.ascontiguousarray(m, np.int32)
         A = np.ascontiguousarray(A, np.int8)
         w = np.ascontiguousarray(w, np.float64)
         h = ctypes.c_void_p()
+        flags = (CREATE_VALU if valu else 0) | (CREATE_PROJECTIVE if projective else 0)
         _check(lib.hom_create(int(n), m.ctypes.data_as(ctypes.c_void_p),
                               A.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
-                              CREATE_VALU if valu else 0, ctypes.byref(h)))
+                              flags, ctypes.byref(h)))
         self.handle = h
         self.n = int(n)
         self.M = int(m.sum())
+        self.projective = bool(projective)
 
     @classmethod
-    def from_workload(cls, sys, valu=False):
-        return cls(sys.n, sys.m, sys.A, sys.w, valu=valu)
+    def from_workload(cls, sys, valu=False, projective=False):
+        return cls(sys.n, sys.m, sys.A, sys.w, valu=valu, projective=projective)
 
     def close(self):
         if self.handle:
@@ -203,6 +206,24 @@ def step(sys: System, c, z, s, precision=FP64, device="cuda"):
     st = torch.empty(P, dtype=torch.int32, device=device)
     _check(lib.hom_step(sys.handle, _ptr(c), P, _ptr(z), _ptr(s), _ptr(dE), _ptr(dN), _ptr(st),
                         precision, _stream()))
+    return dE, dN, st
+
+
+def step_proj(sys: System, c, y, s, device="cuda"):
+    """Euler and Newton directions in homogeneous coordinates at points y [P][n+1] (a handle
+    created with projective=True): [dH~/dy; y^*] dE = [-dH~/ds; 0], [dH~/dy; y^*] dN = [-H~; 0],
+    from the null space of the unified system by Householder reflections.  Returns (dE, dN,
+    status)."""
+    import torch
+    c = _dev_like(c, torch.complex128, device)
+    y = _dev_like(y, torch.complex128, device).reshape(-1, sys.n + 1)
+    P = y.shape[0]
+    s = _dev_like(s, torch.float64, device).reshape(-1).expand(P).contiguous()
+    dE = torch.empty((P, sys.n + 1), dtype=torch.complex128, device=device)
+    dN = torch.empty((P, sys.n + 1), dtype=torch.complex128, device=device)
+    st = torch.empty(P, dtype=torch.int32, device=device)
+    _check(lib.hom_step_proj(sys.handle, _ptr(c), P, _ptr(y), _ptr(s), _ptr(dE), _ptr(dN),
+                             _ptr(st), _stream()))
     return dE, dN, st
 
 

@@ -167,9 +167,11 @@ static std::string validate_system(int n, const int32_t *m, const int8_t *A, con
   return "";
 }
 
-// Exponent table [mmax][n][LD]: exponents as doubles zero padded to N, lifting in slot N.
+// Exponent table [mmax][n][LD]: exponents as doubles zero padded to N, lifting in slot N.  With
+// `hom` (a projective handle) slot n holds the homogenising exponent hom[monomial].
 static void build_table(int n, int N, const int32_t *m, const int8_t *A, const double *w, int mmax,
-                        std::vector<double> &T, std::vector<int32_t> &off) {
+                        std::vector<double> &T, std::vector<int32_t> &off,
+                        const std::vector<int> *hom = nullptr) {
   const int LD = table_ld(N);
   off.assign(n, 0);
   int64_t acc = 0;
@@ -183,6 +185,7 @@ static void build_table(int n, int N, const int32_t *m, const int8_t *A, const d
       double *t = &T[((size_t)i * n + k) * LD];
       const int8_t *a = A + (size_t)(off[k] + i) * n;
       for (int j = 0; j < n; ++j) t[j] = (double)a[j];
+      if (hom) t[n] = (double)(*hom)[off[k] + i];
       t[N] = w[off[k] + i];
     }
 }
@@ -324,16 +327,41 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   g_err.clear();
   if (!out) HOM_FAIL(HOM_EINVAL, "hom_create: out is NULL");
   *out = nullptr;
-  if (flags & ~HOM_CREATE_VALU) HOM_FAIL(HOM_EINVAL, "hom_create: unknown flags");
+  if (flags & ~(HOM_CREATE_VALU | HOM_CREATE_PROJECTIVE))
+    HOM_FAIL(HOM_EINVAL, "hom_create: unknown flags");
   int64_t M = 0;
   int mmax = 0;
   const std::string bad = validate_system(n, m, A, w, &M, &mmax);
   if (!bad.empty()) HOM_FAIL(HOM_EINVAL, "hom_create: " + bad);
-  const int N = bucket_for(n);
+  const bool projective = (flags & HOM_CREATE_PROJECTIVE) != 0;
+  // homogenising exponents (Sec. 2.2): d_k - sum_j a_j with d_k the largest total degree of
+  // equation k, so that each equation is homogeneous of degree d_k in n + 1 unknowns
+  std::vector<int> hom;
+  if (projective) {
+    if (proj_group_size(n) == 0) HOM_FAIL(HOM_EINVAL, "hom_create: projective handles need n <= 29");
+    hom.resize((size_t)M);
+    int64_t o = 0;
+    for (int k = 0; k < n; ++k) {
+      int dk = INT_MIN;
+      for (int i = 0; i < m[k]; ++i) {
+        int t = 0;
+        for (int j = 0; j < n; ++j) t += A[(size_t)(o + i) * n + j];
+        hom[(size_t)(o + i)] = t;
+        dk = std::max(dk, t);
+      }
+      for (int i = 0; i < m[k]; ++i) {
+        hom[(size_t)(o + i)] = dk - hom[(size_t)(o + i)];
+        if (hom[(size_t)(o + i)] > 127)
+          HOM_FAIL(HOM_EINVAL, "hom_create: a homogenising exponent exceeds 127");
+      }
+      o += m[k];
+    }
+  }
+  const int N = projective ? proj_group_size(n) : bucket_for(n);
   const size_t lds = lds_for(N, n, mmax);
   std::vector<double> T;
   std::vector<int32_t> off;
-  build_table(n, N, m, A, w, mmax, T, off);
+  build_table(n, N, m, A, w, mmax, T, off, projective ? &hom : nullptr);
   std::vector<int32_t> A32((size_t)M * n);
   for (size_t i = 0; i < A32.size(); ++i) A32[i] = A[i];
 
@@ -346,6 +374,7 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   // tables beyond the LDS budget stay in global memory (read through the caches)
   S.global_tables = lds > kMaxLds;
   S.lds_bytes = S.global_tables ? 0 : lds;
+  S.projective = projective;
   auto fail = [&](hipError_t e, const char *what) {
     set_error(std::string("hom_create: ") + what + ": " + hipGetErrorString(e));
     free_system(S);
@@ -366,7 +395,7 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
     return fail(e, "hipMemcpy");
   if ((e = hipMemcpy(S.dA, A32.data(), A32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "hipMemcpy");
-  if (mmax >= kDenseMinM && !(flags & HOM_CREATE_VALU)) {
+  if (mmax >= kDenseMinM && !(flags & HOM_CREATE_VALU) && !projective) {
     DenseHost D;
     build_dense(n, m, A, w, off, D);
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -506,6 +535,7 @@ int hom_eval(hom_system_t h, const double *c, int64_t P, const double *z, const 
              double *G, double *logscale, int flags, hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_eval: NULL handle");
+  if (h->s.projective) HOM_FAIL(HOM_EUNSUPPORTED, "hom_eval: projective handles support hom_step_proj only");
   if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_eval: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_eval: P < 0");
   if (flags & ~15) HOM_FAIL(HOM_EINVAL, "hom_eval: unknown flags");
@@ -537,6 +567,7 @@ int hom_step(hom_system_t h, const double *c, int64_t P, const double *z, const 
              hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_step: NULL handle");
+  if (h->s.projective) HOM_FAIL(HOM_EUNSUPPORTED, "hom_step: projective handles support hom_step_proj only");
   if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_step: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_step: P < 0");
   if (precision != HOM_FP64 && precision != HOM_MIXED)
@@ -561,6 +592,27 @@ int hom_step(hom_system_t h, const double *c, int64_t P, const double *z, const 
   HOM_HIP(e, "hom_step");
   HOM_HIP(e2, "hom_step: free workspace");
   HOM_HIP(e3, "hom_step: free workspace");
+  return HOM_OK;
+}
+
+int hom_step_proj(hom_system_t h, const double *c, int64_t P, const double *y, const double *s,
+                  double *dy_euler, double *dy_newton, int32_t *status, hom_stream_t stream) {
+  g_err.clear();
+  if (!h) HOM_FAIL(HOM_EINVAL, "hom_step_proj: NULL handle");
+  if (!h->s.projective)
+    HOM_FAIL(HOM_EUNSUPPORTED, "hom_step_proj: needs a handle created with HOM_CREATE_PROJECTIVE");
+  if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_step_proj: P < 0");
+  if (P == 0) return HOM_OK;
+  if (!c || !y || !s || !dy_euler || !dy_newton || !status)
+    HOM_FAIL(HOM_EINVAL, "hom_step_proj: NULL array");
+  hipStream_t st = (hipStream_t)stream;
+  void *cws = nullptr;
+  hipError_t e = coeff_begin(h->s, c, st, &cws);
+  if (e == hipSuccess)
+    e = launch_step_proj(h->s, cws, c, P, y, s, dy_euler, dy_newton, status, st);
+  hipError_t e2 = coeff_end(cws, st);
+  HOM_HIP(e, "hom_step_proj");
+  HOM_HIP(e2, "hom_step_proj: free workspace");
   return HOM_OK;
 }
 
@@ -607,6 +659,7 @@ static int check_track_args(const char *fn, hom_system_t h, const double *c, int
   const std::string f(fn);
   *nothing_to_do = false;
   if (!h) HOM_FAIL(HOM_EINVAL, f + ": NULL handle");
+  if (h->s.projective) HOM_FAIL(HOM_EUNSUPPORTED, f + ": projective handles support hom_step_proj only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, f + ": P < 0");
   if (!params) HOM_FAIL(HOM_EINVAL, f + ": NULL params");
   const bool batch = h->s.num_sys > 0;
@@ -837,6 +890,7 @@ int hom_endpoint_grad(hom_system_t h, const double *c, int64_t P, const double *
                       const double *grad_x, double *grad_c, int precision, hom_stream_t stream) {
   g_err.clear();
   if (!h) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: NULL handle");
+  if (h->s.projective) HOM_FAIL(HOM_EUNSUPPORTED, "hom_endpoint_grad: projective handles support hom_step_proj only");
   if (h->s.num_sys > 0) HOM_FAIL(HOM_EUNSUPPORTED, "hom_endpoint_grad: batch handles are supported by hom_track only");
   if (P < 0) HOM_FAIL(HOM_EINVAL, "hom_endpoint_grad: P < 0");
   if (precision != HOM_FP64 && precision != HOM_MIXED)

@@ -62,6 +62,9 @@ struct System {
   int32_t *dA = nullptr;    // device [M][n] exponents as int32 (adjoint kernel)
   size_t lds_bytes = 0;     // LDS image of the tables; 0 when they stay in global memory
   bool global_tables = false;
+  // projective handle (hom_create with HOM_CREATE_PROJECTIVE): n equations in n + 1 homogeneous
+  // unknowns; the tables hold the homogenised exponents; N = proj_group_size(n)
+  bool projective = false;
   // cws: this call's table-order coefficients (coeff_ws_bytes), for global_tables only
   SysDev dev(const void *cws = nullptr) const {
     const Cx<double> *Cg = global_tables ? static_cast<const Cx<double> *>(cws) : nullptr;
@@ -148,6 +151,12 @@ hipError_t launch_dense_eval(const System &S, const double *c, int64_t P, const 
 hipError_t launch_dense_step(const System &S, const void *cws, const double *c, int64_t P,
                              const double *z, const double *s, double *dE, double *dN,
                              int32_t *status, int precision, void *dws, hipStream_t stream);
+
+// Projective step (hom_step_proj): group size for n equations (a power of two >= n + 3, or 0).
+int proj_group_size(int n);
+hipError_t launch_step_proj(const System &S, const void *cws, const double *c, int64_t P,
+                            const double *y, const double *s, double *dE, double *dN,
+                            int32_t *status, hipStream_t stream);
 
 // number of compute units of the current device (cached)
 int num_cus();

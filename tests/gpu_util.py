@@ -177,3 +177,20 @@ def dir_bound(kappa, n, unit_roundoff, floor):
     growth factor and the evaluation)."""
     return np.maximum(floor, 16.0 * n * unit_roundoff * np.abs(np.asarray(kappa)))
 
+
+def proj_kappa(sys_, y, s):
+    """kappa_inf of the row-equilibrated projective system [dH~/dy; y^*] at points y [P][n+1]:
+    dH~/dy at y = y_n (x, 1) from the affine evaluation (columns J_z / x, and the homogenising
+    column from Euler's identity d_k h_k - sum_j (J_z)_kj), rows normalised."""
+    n = sys_.n
+    x = y[:, :n] / y[:, n:]
+    z = np.log(x)
+    G, _ = oracle.eval(sys_, sys_.c, z, np.broadcast_to(s, (len(y),)))
+    Jz, H = G[:, :, :n], G[:, :, n + 1]
+    d = np.array([int(sys_.A[sys_.equation(k)].astype(int).sum(1).max()) for k in range(n)])
+    J = np.zeros((len(y), n + 1, n + 1), complex)
+    J[:, :n, :n] = Jz / x[:, None, :]
+    J[:, :n, n] = d[None, :] * H - Jz.sum(2)
+    J[:, n, :] = np.conj(np.concatenate([x, np.ones((len(y), 1))], axis=1))
+    J /= np.abs(J).sum(2, keepdims=True)
+    return np.linalg.cond(J, p=np.inf)

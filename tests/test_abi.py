@@ -43,9 +43,19 @@ def test_invalid_arguments_rejected_without_gpu():
     bad_A = A.copy(); bad_A[0, 0] = -128
     assert lib.hom_create(2, P(m), P(bad_A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
     assert lib.hom_create(2, P(m), P(A), P(w), 4, ctypes.byref(out)) == hom.HOM_EINVAL
+    # projective handles: n <= 29 and homogenising exponents <= 127 (checked before the GPU)
+    m30 = np.full(30, 1, np.int32)
+    A30 = np.zeros((30, 30), np.int8)
+    assert lib.hom_create(30, P(m30), P(A30), P(np.zeros(30)), hom.CREATE_PROJECTIVE,
+                          ctypes.byref(out)) == hom.HOM_EINVAL
+    big = np.array([[100, 100], [-100, -100], [0, 0], [1, 0]], np.int8)  # d = 200: 400 > 127
+    assert lib.hom_create(2, P(m), P(big), P(w), hom.CREATE_PROJECTIVE,
+                          ctypes.byref(out)) == hom.HOM_EINVAL
+    assert b"homogenising exponent" in lib.hom_last_error()
     assert lib.hom_create(2, None, P(A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
     assert lib.hom_eval(None, None, 0, None, None, None, None, 0, None) == hom.HOM_EINVAL
     assert lib.hom_step(None, None, 0, None, None, None, None, None, 0, None) == hom.HOM_EINVAL
+    assert lib.hom_step_proj(None, None, 0, None, None, None, None, None, None) == hom.HOM_EINVAL
     assert lib.hom_destroy(None) == hom.HOM_OK
     p = hom.TrackParams()
     assert lib.hom_track_params_default(ctypes.byref(p), 7) == hom.HOM_EINVAL
