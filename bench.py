@@ -289,6 +289,58 @@ def run_dense(hom, torch, P, reps=3):
     return out
 
 
+# common support (every equation on one support of m = 128 monomials), per point:
+#   A1 2 (2n + 1) m and A2 8 m once, then per equation c_k . E (6 m) and the contraction m (4n + 6)
+U_FLOPS_EVAL = 2 * (2 * C3_N + 1) * C3_M + 8 * C3_M + C3_N * C3_M * (4 * C3_N + 12)
+#   FP64 MFMA issued: A1 16 per 16 x 16 on the m common monomials, A3 16 per 16 x 16 per equation
+U_MFMA_F64 = C3_M * 16 * 2048 / 256 + C3_MONO * 16 * 2048 / 256
+
+
+def run_union(hom, torch, P, reps=3):
+    """Common-support system at n = 32, m = 128 (exponentials shared by the equations): FP64 eval
+    and step on the common-support engine against the per-equation engine on the same system."""
+    import workloads as W
+    sys_, z, s = W.union_config(P=P)
+    dev = "cuda"
+    c = torch.tensor(sys_.c, dtype=torch.complex128, device=dev)
+    zt = torch.tensor(z, dtype=torch.complex128, device=dev)
+    st = torch.tensor(s, dtype=torch.float64, device=dev)
+    out = {}
+    for per_eq in (False, True):
+        h = hom.System.from_workload(sys_, per_equation=per_eq)
+        for kind in ("eval", "step"):
+            name = f"{kind}_{'per_equation' if per_eq else 'common_support'}_fp64"
+
+            def once():
+                r = hom.eval(h, c, zt, st) if kind == "eval" else hom.step(h, c, zt, st)
+                del r
+            once()
+            torch.cuda.synchronize()
+            hom.profile_read()
+            hom.set_profiling(True)
+            for _ in range(reps):
+                once()
+            torch.cuda.synchronize()
+            hom.set_profiling(False)
+            kern = {}
+            for kname, ms, _u in hom.profile_read():
+                kern[kname] = kern.get(kname, 0.0) + ms / reps
+            ms = sum(kern.values())
+            ek = [k for k in kern if k in ("k_union<fp64>", "k_dense<fp64>")]
+            ems = sum(kern[k] for k in ek)
+            rec = {"kernels_ms": kern, "ms": ms, "points_per_s": P / (ms * 1e-3),
+                   "eval_kernel_ms": ems,
+                   "eval_tflops_algorithmic": P * U_FLOPS_EVAL / (ems * 1e-3) / 1e12,
+                   "eval_frac_of_fp64_peak_algorithmic": P * U_FLOPS_EVAL / (ems * 1e-3) / PEAK_FP64}
+            if not per_eq:
+                rec["mfma_frac_of_fp64_peak"] = P * U_MFMA_F64 / (ems * 1e-3) / PEAK_FP64
+            out[name] = rec
+            print(f"# union {name}: {ms:.2f} ms, {rec['points_per_s']:.3e} points/s, kernels {kern}",
+                  file=sys.stderr, flush=True)
+        h.close()
+    return out
+
+
 def run_eval_n10(hom, torch, P=65536, reps=5):
     """hom_eval and hom_step on P random points of the n = 10 system.  The evaluation reads z, s and
     writes G and the row scales (2168 B per point at n = 10): it is judged against HBM bandwidth."""
@@ -651,7 +703,9 @@ def main():
     # the plain FP64 form, the mixed form, and an FP64 control at the mixed form's corrector
     # tolerance (separates the effect of the precision from that of the tolerance)
     legs = (("fp64", hom.FP64, {}), ("mixed", hom.MIXED, {}),
-            ("fp64_tol_track_1e-5", hom.FP64, {"tol_track": 1e-5}))
+            ("fp64_tol_track_1e-5", hom.FP64, {"tol_track": 1e-5}),
+            ("mixed_hermite", hom.MIXED, {"predictor": hom.PREDICT_HERMITE}),
+            ("fp64_hermite", hom.FP64, {"predictor": hom.PREDICT_HERMITE}))
     for name, prec, kw in legs:
         res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup, **kw)
         print(f"# {name}: {res[name]['rate']:.4e} {UNIT}, {res[name]['ms_per_step']:.2f} ms/step, "
@@ -690,16 +744,21 @@ def main():
         "fp64": form_rec(res["fp64"]),
         "mixed": form_rec(mixed),
         "fp64_tol_track_1e-5": form_rec(res["fp64_tol_track_1e-5"]),
+        "mixed_hermite": form_rec(res["mixed_hermite"]),
+        "fp64_hermite": form_rec(res["fp64_hermite"]),
+        "endpoints_mixed_hermite_vs_fp64": compare_endpoints(res["mixed_hermite"], res["fp64"]),
         "endpoints_mixed_vs_fp64": compare_endpoints(mixed, res["fp64"]),
         "endpoints_fp64_tol_track_1e-5_vs_fp64": compare_endpoints(res["fp64_tol_track_1e-5"],
                                                                    res["fp64"]),
         "roofline": roof,
     }
     out["mixed"].pop("roofline_frac_fp64_peak")
+    out["mixed_hermite"].pop("roofline_frac_fp64_peak")
     if not args.no_dense:
         out["eval_step_n10_65536_points"] = run_eval_n10(hom, torch, P=65536)
         out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)
         out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
+        out["common_support_n32_m128"] = run_union(hom, torch, args.dense_points)
         out["step_proj_n10_65536_points"] = run_step_proj(hom, torch)
     if not args.no_batch:
         out["batch_c4"] = run_c4(hom, torch)

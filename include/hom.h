@@ -60,6 +60,7 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
 /* hom_create flags */
 #define HOM_CREATE_VALU 1 /* build no matrix-core tables (see hom_create) */
 #define HOM_CREATE_PROJECTIVE 2 /* the homogenised system in n + 1 unknowns (hom_step_proj only) */
+#define HOM_CREATE_PER_EQUATION 4 /* no common-support engine even when the supports coincide */
 
 /* per-path status (hom_step: OK or SINGULAR; hom_track: all) */
 #define HOM_PATH_OK 0            /* reached s = 0, endgame converged, residual <= res_tol */
@@ -83,7 +84,15 @@ typedef void *hom_stream_t; /* a hipStream_t; NULL is the null stream */
  * tile of 16 points (FP64: 16x16x4 f64 MFMA; HOM_EVAL_FP32 / HOM_MIXED: BF16x3, i.e. z and the
  * exponentials split into three bf16 parts with FP32 accumulation, the phase formed exactly
  * from integer digit sums); hom_step keeps the LU on the vector units.  flags: 0 or
- * HOM_CREATE_VALU (no matrix-core tables), HOM_CREATE_PROJECTIVE (a handle for hom_step_proj).
+ * HOM_CREATE_VALU (no matrix-core tables), HOM_CREATE_PROJECTIVE (a handle for hom_step_proj),
+ * HOM_CREATE_PER_EQUATION (see below).
+ * Common support (the unmixed case of Sec. 5.1): when every equation lists the same monomials in
+ * the same order with the same liftings (n > 1, at most 256 monomials, at least 32), the FP64
+ * matrix-core evaluation forms each point's exponentials e^{<a, z> + w s} once, shared by all
+ * equations, and contracts them with every equation's coefficients and the common exponent
+ * columns (Sec. 5.1: one exponential row e^{Z A} for all of [B_1 ... B_n]); the row shift
+ * logscale is then one value per point, the row maximum over the common support to within about
+ * 0.1.  HOM_CREATE_PER_EQUATION keeps the per-equation engines instead.
  * n in [1, 32]; m[k] >= 1; M <= 65536.  Synchronous.
  * Errors: HOM_EINVAL (bad argument), HOM_ENOMEM, HOM_EDEVICE.
  */
@@ -188,7 +197,17 @@ typedef struct {
                            HOM_TRACK_SIDE_NOWAIT */
     int32_t tile;       /* batched form: paths per work item = tile x lane groups per block
                            (0: the default, 4) */
+    int32_t predictor;  /* HOM_PREDICT_EULER (default) or HOM_PREDICT_HERMITE */
 } hom_track_params;
+
+/* hom_track_params.predictor.  Euler: z = z_a + h dz_euler(z_a) (Sec. 2.3).  Hermite: the cubic
+ * through the last two accepted points (s_p, z_p), (s_a, z_a) with slopes dz_euler there (the
+ * Euler directions the consolidated solve already returned at those points; Sec. 2.3 lists the
+ * cubic Hermite method among the predictors built on them), used when the step h <= 4 (s_a - s_p);
+ * the first step after a path's start or resume is an Euler step (so a resumed run is not
+ * bitwise the uninterrupted one with this predictor, though it reaches the same endpoints). */
+#define HOM_PREDICT_EULER 0
+#define HOM_PREDICT_HERMITE 1
 
 /* hom_track_params.flags: recompute every row's maximum (the e^{-M_k} row shift) at every
  * evaluation instead of reusing the previous evaluation's maximum.  Slower (one more pass over

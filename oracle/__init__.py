@@ -10,7 +10,8 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   eval            pinned: central finite differences, 50-digit mpmath, exact values at x = +-1,
                   branch invariance, J_x = J_z diag(e^{-z}), zeros at binomial roots
   step            pinned: LAPACK solve, Cramer's rule, closed-form directions of binomial systems
-  track           pinned: closed-form binomial paths, mixed-volume root count, residuals
+  track           pinned: closed-form binomial paths, mixed-volume root count, residuals; the
+                  Hermite predictor against scipy's CubicHermiteSpline and exactness on cubics
   endpoint_grad   pinned: central finite differences of re-solved endpoints
   step_proj       pinned: homogeneity of degree one under y -> lambda y, the affine directions
                   mapped into homogeneous coordinates (from the affine evaluation and numpy
@@ -63,6 +64,8 @@ def _load():
         _lib.oracle_residual.argtypes = [i32, P, P, P, i64, P, P, i32]
         _lib.oracle_endpoint_grad.argtypes = [i32, P, P, P, P, i64, P, P, P]
         _lib.oracle_step_proj.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
+        _lib.oracle_hermite.argtypes = [i32, i64, P, P, P, P, P, P, P, P]
+        _lib.oracle_hermite.restype = i32
         for name in ("oracle_eval", "oracle_step", "oracle_track", "oracle_residual",
                      "oracle_endpoint_grad", "oracle_step_proj"):
             getattr(_lib, name).restype = i32
@@ -129,6 +132,20 @@ def step(sys, c, z, s, threads=None):
     return dE, dN, st, ratio
 
 
+def hermite(s0, z0, e0, s1, z1, e1, s):
+    """The tracker's cubic Hermite predictor: the cubic through (s0, z0), (s1, z1) with slopes
+    e0, e1, at s.  Arrays [P][n] (complex) and [P] (s values)."""
+    lib = _load()
+    z0 = np.ascontiguousarray(z0, np.complex128)
+    P, n = z0.shape
+    args = [np.ascontiguousarray(np.broadcast_to(v, (P,)), np.float64) for v in (s0, s1, s)]
+    e0, z1, e1 = (np.ascontiguousarray(v, np.complex128) for v in (e0, z1, e1))
+    out = np.zeros((P, n), np.complex128)
+    _checked(lib.oracle_hermite(n, P, _ptr(args[0]), _ptr(z0), _ptr(e0), _ptr(args[1]), _ptr(z1),
+                                _ptr(e1), _ptr(args[2]), _ptr(out)))
+    return out
+
+
 def step_proj(sys, c, y, s, threads=None):
     """Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)) at points
     y [P][n+1] (y_j pairs with x_j for j < n; y_n is the homogenising coordinate, so an affine
@@ -173,13 +190,14 @@ class TrackParams:
     max_end: int = 8
     max_steps: int = 100000
     max_iters: int = 100000
+    predictor: int = 0  # 0 Euler, 1 cubic Hermite through the last two accepted points
 
     def arrays(self):
         d = np.array([self.ds0, self.ds_max, self.ds_min, self.tol_polish, self.tol_track,
                       self.tol_end, self.res_tol, self.div_re, self.sing_ratio,
                       self.tol_predict], np.float64)
         i = np.array([self.max_polish, self.max_newton, self.max_end, self.max_steps,
-                      self.max_iters], np.int32)
+                      self.max_iters, self.predictor], np.int32)
         return d, i
 
 

@@ -16,9 +16,10 @@
  *            Newton direction dN solves J_z dN = -H (Sec. 2.3).  Both come from one LU with partial
  *            pivoting of the augmented matrix [J_z | H_s | H] (the unified system of Sec. 6, in
  *            its affine form).
- *   - track: a predictor-corrector loop over s in [s0, 0] that uses dE as Euler predictor and dN
- *            as Newton corrector (Sec. 2.3); the paper gives no step control, so the constants
- *            and rules are taken from the parameter struct below.
+ *   - track: a predictor-corrector loop over s in [s0, 0] that uses dE as Euler predictor (or,
+ *            optionally, the cubic Hermite predictor through the last two accepted points and
+ *            their Euler directions, Sec. 2.3) and dN as Newton corrector (Sec. 2.3); the paper
+ *            gives no step control, so the constants and rules come from the parameter struct.
  *   - proj : the Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)):
  *            the homogenised system's Jacobian with the row y^*, one (n+1) x (n+1) solve for
  *            both (the unified system of Sec. 6, solved plainly instead of by QR).
@@ -382,7 +383,34 @@ typedef struct {
     double sing_ratio;  /* min/max |pivot| below this => singular */
     double tol_predict; /* a predicted point whose first correction exceeds this is rejected */
     int max_polish, max_newton, max_end, max_steps, max_iters;
+    int predictor;      /* 0: Euler; 1: cubic Hermite through the last two accepted points */
 } or_params;
+
+/* Cubic Hermite predictor (the predictor family of Sec. 2.3 built on the Euler direction): the
+ * cubic through (s0, z0) and (s1, z1) with slopes e0 and e1 (dz/ds at those points, s0 < s1),
+ * evaluated at s (past s1: an extrapolation).  With t = (s - s0) / (s1 - s0) and
+ * d = s1 - s0 the Hermite basis gives
+ *   z(s) = (2t^3 - 3t^2 + 1) z0 + (t^3 - 2t^2 + t) d e0 + (-2t^3 + 3t^2) z1 + (t^3 - t^2) d e1. */
+static void hermite(int n, double s0, const cplx *z0, const cplx *e0, double s1, const cplx *z1,
+                    const cplx *e1, double s, cplx *out) {
+    const double d = s1 - s0, t = (s - s0) / d;
+    const double t2 = t * t, t3 = t2 * t;
+    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t;
+    const double h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+    for (int j = 0; j < n; j++)
+        out[j] = h00 * z0[j] + h10 * d * e0[j] + h01 * z1[j] + h11 * d * e1[j];
+}
+
+/* The predictor alone, for its tests: P independent evaluations (complex arrays [P][n]). */
+int oracle_hermite(int n, int64_t P, const double *s0, const double *z0, const double *e0,
+                   const double *s1, const double *z1, const double *e1, const double *s,
+                   double *out) {
+    if (n < 1 || n > OR_NMAX) return -1;
+    for (int64_t p = 0; p < P; p++)
+        hermite(n, s0[p], (const cplx *)z0 + p * n, (const cplx *)e0 + p * n, s1[p],
+                (const cplx *)z1 + p * n, (const cplx *)e1 + p * n, s[p], (cplx *)out + p * n);
+    return 0;
+}
 
 enum { OR_OK = 0, OR_START = 1, OR_RUNNING = 2, OR_SINGULAR = -1, OR_STEP_MIN = -2,
        OR_DIVERGED = -3, OR_NONFINITE = -4, OR_POLISH_FAIL = -5, OR_ENDGAME_FAIL = -6,
@@ -405,7 +433,9 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
                        int32_t *cnt) {
     if (*status != OR_START && *status != OR_RUNNING) return;
     cplx za[OR_NMAX], dEa[OR_NMAX], dE[OR_NMAX], dN[OR_NMAX];
-    double s = *s_io, sa = s, ds = *ds_io, nrm_prev = 0.0;
+    cplx zp[OR_NMAX], dEp[OR_NMAX]; /* the accepted point before (z_a, s_a), for the Hermite predictor */
+    double s = *s_io, sa = s, ds = *ds_io, nrm_prev = 0.0, sp = 0.0;
+    int have_a = 0, have_p = 0;     /* accepted points held in (za, sa) and (zp, sp) */
     int phase = (*status == OR_START) ? PH_POLISH : PH_RESUME;
     if (*status == OR_START) ds = pr->ds0;
     int k = 0, steps_here = 0;
@@ -443,6 +473,8 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
             /* (z, s) is an accepted point: keep it and predict with its Euler direction */
             for (int j = 0; j < n; j++) { za[j] = z[j]; dEa[j] = dE[j]; }
             sa = s;
+            have_a = 1;
+            have_p = 0;
             if (sa >= 0.0) { phase = PH_END; k = 0; goto endgame; }
             if (steps_here >= pr->max_steps) { *status = OR_RUNNING; break; }
             goto predict;
@@ -454,9 +486,15 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
          * lie nearer another path than its own, so the step is rejected before any correction */
         if (k == 0 && nrm > pr->tol_predict) goto reject;
         if (nrm <= pr->tol_track) {
-            /* accept the evaluated point */
+            /* accept the evaluated point (the previous one is kept for the Hermite predictor) */
+            if (have_a) {
+                for (int j = 0; j < n; j++) { zp[j] = za[j]; dEp[j] = dEa[j]; }
+                sp = sa;
+                have_p = 1;
+            }
             for (int j = 0; j < n; j++) { za[j] = z[j]; dEa[j] = dE[j]; }
             sa = s;
+            have_a = 1;
             cnt[0]++;
             steps_here++;
             if (k <= 1) ds = fmin(2.0 * ds, pr->ds_max);
@@ -482,8 +520,12 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
         s = sa;
     predict: {
         double h = fmin(ds, -sa);
-        for (int j = 0; j < n; j++) z[j] = za[j] + h * dEa[j];
-        s = (h == -sa) ? 0.0 : sa + h;
+        const double st = (h == -sa) ? 0.0 : sa + h;
+        if (pr->predictor == 1 && have_p && h <= 4.0 * (sa - sp))
+            hermite(n, sp, zp, dEp, sa, za, dEa, st, z);  /* cubic through the last two points */
+        else
+            for (int j = 0; j < n; j++) z[j] = za[j] + h * dEa[j];
+        s = st;
         k = 0;
         phase = PH_TRACK;
         continue;
@@ -506,7 +548,8 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
 }
 
 /* Track P paths.  dparams: ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re,
- * sing_ratio, tol_predict; iparams: max_polish, max_newton, max_end, max_steps, max_iters. */
+ * sing_ratio, tol_predict; iparams: max_polish, max_newton, max_end, max_steps, max_iters,
+ * predictor (0 Euler, 1 cubic Hermite). */
 int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
                  int64_t P, double *z, double *s, double *ds, const double *dparams,
                  const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {
@@ -527,6 +570,7 @@ int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, cons
     pr.max_end = iparams[2];
     pr.max_steps = iparams[3];
     pr.max_iters = iparams[4];
+    pr.predictor = iparams[5];
 #pragma omp parallel for schedule(dynamic, 16) num_threads(threads > 0 ? threads : 1)
     for (int64_t p = 0; p < P; p++)
         track_path(n, m, A, w, (const cplx *)c, &pr, (cplx *)z + p * n, s + p, ds + p,

@@ -20,16 +20,18 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhom.so")
+# HOM_LIBRARY selects another build of the library (e.g. one compiled with different options)
+LIB_PATH = os.environ.get("HOM_LIBRARY") or os.path.join(_HERE, "libhom.so")
 
 HOM_OK, HOM_EINVAL, HOM_ENOMEM, HOM_EDEVICE, HOM_EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
 UNSCALED, AFFINE, EVAL_FP32, EVAL_VALU = 1, 2, 4, 8
-CREATE_VALU, CREATE_PROJECTIVE = 1, 2
+CREATE_VALU, CREATE_PROJECTIVE, CREATE_PER_EQUATION = 1, 2, 4
 PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
 TRACK_EXACT_SHIFT, TRACK_SERIAL, TRACK_SIDE_NOWAIT = 1, 2, 4
+PREDICT_EULER, PREDICT_HERMITE = 0, 1
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_step_proj", "hom_track_params_default", "hom_track", "hom_track_noalloc",
@@ -50,7 +52,8 @@ class TrackParams(ctypes.Structure):
                 ("tol_predict", ctypes.c_double), ("max_polish", ctypes.c_int32), ("max_newton", ctypes.c_int32),
                 ("max_end", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("predictor", ctypes.c_int32)]
 
 
 class SysDesc(ctypes.Structure):
@@ -118,12 +121,13 @@ class System:
 
     num_sys = 1
 
-    def __init__(self, n, m, A, w, valu=False, projective=False):
+    def __init__(self, n, m, A, w, valu=False, projective=False, per_equation=False):
         m = np.ascontiguousarray(m, np.int32)
         A = np.ascontiguousarray(A, np.int8)
         w = np.ascontiguousarray(w, np.float64)
         h = ctypes.c_void_p()
-        flags = (CREATE_VALU if valu else 0) | (CREATE_PROJECTIVE if projective else 0)
+        flags = ((CREATE_VALU if valu else 0) | (CREATE_PROJECTIVE if projective else 0) |
+                 (CREATE_PER_EQUATION if per_equation else 0))
         _check(lib.hom_create(int(n), m.ctypes.data_as(ctypes.c_void_p),
                               A.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
                               flags, ctypes.byref(h)))
@@ -133,8 +137,9 @@ class System:
         self.projective = bool(projective)
 
     @classmethod
-    def from_workload(cls, sys, valu=False, projective=False):
-        return cls(sys.n, sys.m, sys.A, sys.w, valu=valu, projective=projective)
+    def from_workload(cls, sys, valu=False, projective=False, per_equation=False):
+        return cls(sys.n, sys.m, sys.A, sys.w, valu=valu, projective=projective,
+                   per_equation=per_equation)
 
     def close(self):
         if self.handle:

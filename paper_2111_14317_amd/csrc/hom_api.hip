@@ -327,7 +327,7 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
   g_err.clear();
   if (!out) HOM_FAIL(HOM_EINVAL, "hom_create: out is NULL");
   *out = nullptr;
-  if (flags & ~(HOM_CREATE_VALU | HOM_CREATE_PROJECTIVE))
+  if (flags & ~(HOM_CREATE_VALU | HOM_CREATE_PROJECTIVE | HOM_CREATE_PER_EQUATION))
     HOM_FAIL(HOM_EINVAL, "hom_create: unknown flags");
   int64_t M = 0;
   int mmax = 0;
@@ -395,6 +395,19 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
     return fail(e, "hipMemcpy");
   if ((e = hipMemcpy(S.dA, A32.data(), A32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "hipMemcpy");
+  // a common support: every equation lists the same monomials in the same order, same liftings
+  bool same = !projective && n > 1 && !(flags & HOM_CREATE_PER_EQUATION);
+  for (int k = 1; k < n && same; ++k) {
+    if (m[k] != m[0]) {
+      same = false;
+      break;
+    }
+    same = memcmp(A + (size_t)off[k] * n, A, (size_t)m[0] * n) == 0 &&
+           memcmp(w + off[k], w, (size_t)m[0] * sizeof(double)) == 0;
+  }
+  S.union_support = same && mmax >= kDenseMinM && !(flags & HOM_CREATE_VALU) &&
+                    (size_t)((m[0] + 31) / 32 * 32) * 16 * 16 <= kUnionLdsBytes;
+  S.union_tiles = S.union_support ? (m[0] + 31) / 32 * 2 : 0;
   if (mmax >= kDenseMinM && !(flags & HOM_CREATE_VALU) && !projective) {
     DenseHost D;
     build_dense(n, m, A, w, off, D);
@@ -639,6 +652,7 @@ int hom_track_params_default(hom_track_params *p, int precision) {
   p->precision = precision;
   p->flags = 0;
   p->tile = 0;
+  p->predictor = HOM_PREDICT_EULER;
   return HOM_OK;
 }
 
@@ -647,7 +661,8 @@ static TrackDev to_dev(const hom_track_params *p) {
                   p->tol_end,    p->res_tol,    p->div_re,  p->sing_ratio, p->tol_predict,
                   p->max_polish,
                   p->max_newton, p->max_end,    p->max_steps, p->max_iters,
-                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3, 0};
+                  (p->flags & HOM_TRACK_EXACT_SHIFT) ? 1 : 0, p->tile, 3, 0, nullptr, nullptr,
+                  0ull, 0, 0, 0ull, p->predictor};
 }
 
 // Checks of hom_track's arguments shared by its allocation-free variant.  Returns HOM_OK (then
@@ -673,7 +688,8 @@ static int check_track_args(const char *fn, hom_system_t h, const double *c, int
       params->max_newton < 1 || params->max_end < 1 || params->max_polish < 1 ||
       params->max_steps < 0 || params->max_iters < 1 ||
       (params->flags & ~(HOM_TRACK_EXACT_SHIFT | HOM_TRACK_SERIAL | HOM_TRACK_SIDE_NOWAIT)) ||
-      params->tile < 0)
+      params->tile < 0 ||
+      (params->predictor != HOM_PREDICT_EULER && params->predictor != HOM_PREDICT_HERMITE))
     HOM_FAIL(HOM_EINVAL, f + ": bad params");
   if (P == 0) {
     *nothing_to_do = true;

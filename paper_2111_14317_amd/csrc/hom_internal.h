@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "../../include/hom.h"
 #include "hom_device.h"
 
 namespace hom {
@@ -31,6 +32,9 @@ struct BatchSysDev {
 // first monomial (coefficient 0), so 16-monomial tiles and 32-monomial chunks never straddle two
 // equations.  Lane layouts are those of the gfx950 16x16 MFMA operands.
 constexpr int kDenseMinM = 32;
+// LDS of one wave of the common-support engine: the point tile's exponentials (16 points x the
+// padded support, complex double)
+constexpr size_t kUnionLdsBytes = 64 * 1024;
 struct DenseDev {
   int n;                 // unknowns
   int nct;               // 16-column tiles of the Jacobian (ceil(n / 16))
@@ -76,6 +80,11 @@ struct System {
   int Md = 0;
   void *dDense = nullptr;  // one allocation holding every DenseDev array
   DenseDev dense{};
+  // union support (Sec. 5.1's unmixed case): every equation has the same monomials, in the same
+  // order, with the same liftings; the dense FP64 engine then forms each point's exponentials once
+  // and contracts them with every equation's coefficients (k_union_f64)
+  bool union_support = false;
+  int union_tiles = 0;  // 16-monomial tiles of the common support (padded to a multiple of 32)
   bool has_dense() const { return dDense != nullptr; }
 };
 
@@ -102,6 +111,7 @@ struct TrackDev {
   // progress (a new park-list entry, a finished wave) before it stops claiming; whatever it
   // leaves is re-tracked by the FP64 launch that follows both
   unsigned long long patience;
+  int predictor;  // HOM_PREDICT_EULER or HOM_PREDICT_HERMITE
 };
 constexpr unsigned long long kSidePatience = 20000000ull;  // 0.2 s
 

@@ -185,6 +185,62 @@ __device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restri
   }
 }
 
+// Writes one equation's row block of a 16-point tile (the FP64 engines' accumulator layout):
+// like store_row, with the column scale e^{M} formed once per lane and passed by shuffle, and
+// the e^{-z_j} factors of HOM_AFFINE formed one (row, column tile) at a time with the polynomial
+// exp and sin/cos, so that the store stays small next to the contraction's registers.
+template <typename OutT, int NCT, class Coef>
+__device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__restrict__ logscale,
+                                               int flags, int64_t p0, int64_t pb, int64_t p1,
+                                               int n, int k, int q, int c16,
+                                               const f64x4_t (&aR)[2], const f64x4_t (&aI)[2],
+                                               Cx<double> H, Cx<double> Hs, double m, double sp,
+                                               const double *__restrict__ z, Coef kc) {
+  const int ld = n + 2;
+  const double own = (flags & 1) ? exp_eval(m, kc) : 1.0;  // e^{M} of this lane's point
+#pragma unroll 1
+  for (int rc = 0; rc < 4 * NCT; ++rc) {
+    const int r = rc / NCT, ct = rc % NCT;
+    const int pr = row_f64(q, r);
+    const int64_t p = pb + pr;
+    const double scale = __shfl(own, pr);
+    const int col = 16 * ct + c16;
+    double vr = aR[0][0], vi = aI[0][0];
+#pragma unroll
+    for (int u = 0; u < 4 * NCT; ++u)
+      if (u == rc) {
+        vr = aR[u % NCT][u / NCT];
+        vi = aI[u % NCT][u / NCT];
+      }
+    if (p < p1 && col < n) {
+      Cx<double> v = {vr * scale, vi * scale};
+      if (flags & 2) {  // times e^{-z_col}
+        const double *zp = z + 2 * (p * n + col);
+        double t = -zp[1] * kInv2Pi;
+        t -= rint(t);
+        double sn, cs;
+        sincos_turns(t, sn, cs, kc);
+        const double mag = exp_eval(-zp[0], kc);
+        v = cmul(v, Cx<double>{mag * cs, mag * sn});
+      }
+      OutT *g = G + 2 * (((p - p0) * n + k) * ld + col);
+      g[0] = (OutT)v.x;
+      g[1] = (OutT)v.y;
+    }
+  }
+  const int64_t p = pb + c16;
+  if (q == 0 && p < p1) {
+    const double fs = (flags & 2) ? own * exp_eval(-sp, kc) : own;  // H_t = e^{-s} H_s
+    OutT *g = G + 2 * (((p - p0) * n + k) * ld + n);
+    g[0] = (OutT)(Hs.x * fs);
+    g[1] = (OutT)(Hs.y * fs);
+    g[2] = (OutT)(H.x * own);
+    g[3] = (OutT)(H.y * own);
+    if (logscale) logscale[p * n + k] = (flags & 1) ? 0.0 : m;
+  }
+}
+
+
 // ------------------------------------------------------------------------------------------
 // BF16x3 engine
 // ------------------------------------------------------------------------------------------
@@ -355,13 +411,22 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 // ------------------------------------------------------------------------------------------
 // FP64 engine
 // ------------------------------------------------------------------------------------------
-template <typename OutT>
-__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2)))
+#ifndef HOM_DENSE_F64_WAVES
+#define HOM_DENSE_F64_WAVES 2
+#endif
+#ifndef HOM_DENSE_F64_KLDS
+#define HOM_DENSE_F64_KLDS 0
+#endif
+template <typename OutT, int NCT>
+__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(HOM_DENSE_F64_WAVES)))
     k_dense_f64(DenseDev D, const Cx<double> *__restrict__ Cd, int64_t p0, int64_t p1,
                 const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
                 double *__restrict__ logscale, int flags, unsigned long long *units) {
+  __shared__ double sK[kCoefCount];  // the polynomial constants of exp and sin/cos
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
-  const int n = D.n, nct = D.nct, nks = D.nks;
+  const int n = D.n, nks = D.nks;  // NCT = D.nct
+  stage_coefficients(sK);
+  __syncthreads();
   const int64_t ntile = (p1 - p0 + 15) >> 4;
   const f64x4_t zero = {0.0, 0.0, 0.0, 0.0};
   for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile;
@@ -393,33 +458,69 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       const double Mk = (double)row_max(D, t0, t1, lane, q, Bzh, sf);
       f64x4_t aR[2] = {zero, zero}, aI[2] = {zero, zero};
       Cx<double> H = {0.0, 0.0}, Hs = {0.0, 0.0};
+#ifndef HOM_DENSE_F64_PF
+#define HOM_DENSE_F64_PF 1
+#endif
+      // the operand tables of the next tile are loaded while this one is processed
+      double eaN[8], cbN[8];
+      if (HOM_DENSE_F64_PF) {
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) eaN[ks] = ks < nks ? D.EAd[(t0 * 8 + ks) * 64 + lane] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          cbN[u] = (u & 1) < NCT ? D.CBd[((t0 * 4 + (u >> 1)) * 2 + (u & 1)) * 64 + lane] : 0.0;
+      }
 #pragma unroll 1
       for (int t = t0; t < t1; ++t) {
+        double eaC[8], cbC[8];
+        if (HOM_DENSE_F64_PF) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            eaC[u] = eaN[u];
+            cbC[u] = cbN[u];
+          }
+          if (t + 1 < t1) {
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+              if (ks < nks) eaN[ks] = D.EAd[((t + 1) * 8 + ks) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if ((u & 1) < NCT) cbN[u] = D.CBd[(((t + 1) * 4 + (u >> 1)) * 2 + (u & 1)) * 64 + lane];
+          }
+        }
         // two accumulator chains per product (even / odd K steps) so that consecutive MFMAs
         // do not wait for each other's results
         f64x4_t dr0 = zero, di0 = zero, dr1 = zero, di1 = zero;
 #pragma unroll
         for (int ks = 0; ks < 8; ks += 2) {
           if (ks < nks) {
-            const double ea = D.EAd[(t * 8 + ks) * 64 + lane];
+            const double ea = HOM_DENSE_F64_PF ? eaC[ks] : D.EAd[(t * 8 + ks) * 64 + lane];
             dr0 = mfma_f64(ea, zr[ks], dr0);
             di0 = mfma_f64(ea, zt[ks], di0);
           }
           if (ks + 1 < nks) {
-            const double ea = D.EAd[(t * 8 + ks + 1) * 64 + lane];
+            const double ea = HOM_DENSE_F64_PF ? eaC[ks + 1] : D.EAd[(t * 8 + ks + 1) * 64 + lane];
             dr1 = mfma_f64(ea, zr[ks + 1], dr1);
             di1 = mfma_f64(ea, zt[ks + 1], di1);
           }
         }
         const f64x4_t dr = dr0 + dr1, di = di0 + di1;
-#pragma unroll 1  // one element at a time: two waves per SIMD fit
+#ifndef HOM_DENSE_F64_UNROLL
+#define HOM_DENSE_F64_UNROLL 1
+#endif
+#pragma unroll HOM_DENSE_F64_UNROLL
         for (int r = 0; r < 4; ++r) {
           const int i = t * 16 + row_f64(q, r);
           const double w = D.W[i];
-          const double mag = exp_eval(fma(w, sp, dr[r] - Mk));
+#if HOM_DENSE_F64_KLDS
+          const CoefLds kc{sK, PointLds{}.fresh()};  // constants read at their use
+#else
+          const CoefConst kc{};
+#endif
+          const double mag = exp_eval(fma(w, sp, dr[r] - Mk), kc);
           const double ph = di[r] - rint(di[r]);
           double sn, cs;
-          sincos_turns(ph, sn, cs);
+          sincos_turns(ph, sn, cs, kc);
           const Cx<double> cc = Cd[i];
           const double cr = cc.x * mag, ci = cc.y * mag;
           const double vr = cr * cs - ci * sn, vi = cr * sn + ci * cs;
@@ -428,12 +529,11 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
           Hs.x = fma(w, vr, Hs.x);
           Hs.y = fma(w, vi, Hs.y);
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            if (ct < nct) {
-              const double cb = D.CBd[((t * 4 + r) * 2 + ct) * 64 + lane];
-              aR[ct] = mfma_f64(vr, cb, aR[ct]);
-              aI[ct] = mfma_f64(vi, cb, aI[ct]);
-            }
+          for (int ct = 0; ct < NCT; ++ct) {
+            const double cb =
+                HOM_DENSE_F64_PF ? cbC[2 * r + ct] : D.CBd[((t * 4 + r) * 2 + ct) * 64 + lane];
+            aR[ct] = mfma_f64(vr, cb, aR[ct]);
+            aI[ct] = mfma_f64(vi, cb, aI[ct]);
           }
         }
       }
@@ -445,10 +545,151 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       Hs.x += __shfl_xor(Hs.x, 32);
       Hs.y += __shfl_xor(Hs.y, 16);
       Hs.y += __shfl_xor(Hs.y, 32);
-      store_row<OutT, f64x4_t, true>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI, H, Hs,
-                               Mk, sp, z);
+      store_row_lean<OutT, NCT>(G, logscale, flags, p0, pb, p1, n, k, q, c16, aR, aI, H, Hs, Mk,
+                                sp, z, CoefLds{sK, PointLds{}.fresh()});
     }
     if (units && lane == 0) {
+      const int64_t cnt = p1 - pb < 16 ? p1 - pb : 16;
+      atomicAdd(units, (unsigned long long)cnt);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Common-support FP64 engine (Sec. 5.1's unmixed case): a block of four waves per tile of 16
+// points.
+//   A1  u = A z + w s for the common monomials   FP64 MFMA (equation 0's tables: all alike)
+//   A2  E = e^{u - M}, one shift M per point      FP64 vector units, once for all equations;
+//                                                 the four waves split the monomial tiles and
+//                                                 leave E in LDS
+//   A3  per equation k: V = c_k . E, then V [a | w | 1] on the matrix cores (J_z) and the
+//       vector units (H_s, H), as in the per-equation engine; the waves split the equations.
+// The exponentials are formed once per (point, monomial) instead of once per (point, monomial,
+// equation); the LDS tile of E is shared by the four waves, so that a CU holds enough waves to
+// hide the latency of the contraction.
+// ------------------------------------------------------------------------------------------
+constexpr int kUnionWaves = 4;
+constexpr int kUnionBlock = 64 * kUnionWaves;
+constexpr size_t kCuLdsBytes = 160 * 1024;  // LDS of one CU
+constexpr size_t kUnionCoefBytes = (kCoefCount * 8 + 15) / 16 * 16;
+#ifndef HOM_UNION_WAVES
+#define HOM_UNION_WAVES 3
+#endif
+
+template <typename OutT, int NCT>
+__global__ void __launch_bounds__(kUnionBlock) __attribute__((amdgpu_waves_per_eu(HOM_UNION_WAVES)))
+    k_union_f64(DenseDev D, const Cx<double> *__restrict__ Cd, int64_t p0, int64_t p1,
+                const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
+                double *__restrict__ logscale, int flags, unsigned long long *units) {
+  extern __shared__ __align__(16) char smem[];
+  double *sK = reinterpret_cast<double *>(smem);  // the polynomial constants of exp and sin/cos
+  Cx<double> *sE = reinterpret_cast<Cx<double> *>(smem + kUnionCoefBytes);  // [tiles][4][64]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
+  const int n = D.n, nks = D.nks;  // NCT = D.nct
+  const int t0 = D.tile0[0], t1 = D.tile0[1];  // the common support's 16-monomial tiles
+  const int64_t ntile = (p1 - p0 + 15) >> 4;
+  const f64x4_t zero = {0.0, 0.0, 0.0, 0.0};
+  stage_coefficients(sK);
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t pb = p0 + tile * 16, pl = pb + c16;
+    const bool lv = pl < p1;
+    uint32_t zh[4];
+    load_hi(z, pl, lv, n, q, zh);
+    const bf16x8_t Bzh = pack8(zh);
+    double zr[8], zt[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int j = q + 4 * ks;
+      double xr = 0.0, t = 0.0;
+      if (lv && j < n) {
+        xr = z[2 * (pl * n + j)];
+        t = z[2 * (pl * n + j) + 1] * kInv2Pi;
+        t -= rint(t);
+      }
+      zr[ks] = xr;
+      zt[ks] = t;
+    }
+    const double sp = lv ? s[pl] : 0.0;
+    const float sf = (float)sp;
+    // one shift per point: the support's row maximum (hi parts of Re z, + w s); every wave forms
+    // it from the same operands in the same order, so the four copies agree bit for bit
+    const double Mp = (double)row_max(D, t0, t1, lane, q, Bzh, sf);
+    // ---- A1 + A2 once, this wave's share of the tiles ----
+#pragma unroll 1
+    for (int t = t0 + wv; t < t1; t += kUnionWaves) {
+      f64x4_t dr0 = zero, di0 = zero, dr1 = zero, di1 = zero;
+#pragma unroll
+      for (int ks = 0; ks < 8; ks += 2) {
+        if (ks < nks) {
+          const double ea = D.EAd[(t * 8 + ks) * 64 + lane];
+          dr0 = mfma_f64(ea, zr[ks], dr0);
+          di0 = mfma_f64(ea, zt[ks], di0);
+        }
+        if (ks + 1 < nks) {
+          const double ea = D.EAd[(t * 8 + ks + 1) * 64 + lane];
+          dr1 = mfma_f64(ea, zr[ks + 1], dr1);
+          di1 = mfma_f64(ea, zt[ks + 1], di1);
+        }
+      }
+      const f64x4_t dr = dr0 + dr1, di = di0 + di1;
+#pragma unroll 2
+      for (int r = 0; r < 4; ++r) {
+        const int i = t * 16 + row_f64(q, r);
+        const CoefLds kc{sK, PointLds{}.fresh()};  // constants read at their use, not hoisted
+        const double mag = exp_eval(fma(D.W[i], sp, dr[r] - Mp), kc);
+        const double ph = di[r] - rint(di[r]);
+        double sn, cs;
+        sincos_turns(ph, sn, cs, kc);
+        sE[((t - t0) * 4 + r) * 64 + lane] = Cx<double>{mag * cs, mag * sn};
+      }
+    }
+    __syncthreads();
+    // ---- A3, this wave's equations ----
+    for (int k = wv; k < n; k += kUnionWaves) {
+      const int ck = D.tile0[k] * 16 - t0 * 16;  // equation k's slots, relative to the support
+      f64x4_t aR[2] = {zero, zero}, aI[2] = {zero, zero};
+      Cx<double> H = {0.0, 0.0}, Hs = {0.0, 0.0};
+#pragma unroll 1
+      for (int t = t0; t < t1; ++t) {
+        Cx<double> e[4], cc[4];
+        double cb[8], w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {  // every operand of the tile first, then the arithmetic
+          const int i = t * 16 + row_f64(q, r);
+          e[r] = sE[((t - t0) * 4 + r) * 64 + lane];
+          cc[r] = Cd[ck + i];
+          w[r] = D.W[i];
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) cb[2 * r + ct] = D.CBd[((t * 4 + r) * 2 + ct) * 64 + lane];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const Cx<double> v = cmul(cc[r], e[r]);
+          H.x += v.x;
+          H.y += v.y;
+          Hs.x = fma(w[r], v.x, Hs.x);
+          Hs.y = fma(w[r], v.y, Hs.y);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            aR[ct] = mfma_f64(v.x, cb[2 * r + ct], aR[ct]);
+            aI[ct] = mfma_f64(v.y, cb[2 * r + ct], aI[ct]);
+          }
+        }
+      }
+      H.x += __shfl_xor(H.x, 16);
+      H.x += __shfl_xor(H.x, 32);
+      H.y += __shfl_xor(H.y, 16);
+      H.y += __shfl_xor(H.y, 32);
+      Hs.x += __shfl_xor(Hs.x, 16);
+      Hs.x += __shfl_xor(Hs.x, 32);
+      Hs.y += __shfl_xor(Hs.y, 16);
+      Hs.y += __shfl_xor(Hs.y, 32);
+      store_row_lean<OutT, NCT>(G, logscale, flags, p0, pb, p1, n, k, q, c16, aR, aI, H, Hs, Mp,
+                                sp, z, CoefLds{sK, PointLds{}.fresh()});
+    }
+    __syncthreads();  // E of this tile is read by every wave before the next tile overwrites it
+    if (units && threadIdx.x == 0) {
       const int64_t cnt = p1 - pb < 16 ? p1 - pb : 16;
       atomicAdd(units, (unsigned long long)cnt);
     }
@@ -614,10 +855,26 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
   } else if (engine == 1) {
     hipLaunchKernelGGL((k_dense_bf16<OutT, false>), grid, block, 0, stream, S.dense, Cf, p0, p1, z,
                        s, G, logscale, flags, units);
-  } else
-    hipLaunchKernelGGL((k_dense_f64<OutT>), grid, block, 0, stream, S.dense, Cd, p0, p1, z, s, G,
-                       logscale, flags, units);
-  prof_end(stream, engine == 1 ? "k_dense<bf16x3>" : "k_dense<fp64>");
+  } else if (S.union_support) {  // common support: the exponentials once per point
+    const size_t lds = kUnionCoefBytes + (size_t)S.union_tiles * 4 * 64 * 16;
+    const int64_t tiles = (p1 - p0 + 15) / 16;
+    const int64_t per_cu = (int64_t)(kCuLdsBytes / lds) < 8 ? (int64_t)(kCuLdsBytes / lds) : 8;
+    const int64_t cap = (int64_t)num_cus() * (per_cu > 0 ? per_cu : 1);
+    const dim3 gu((unsigned)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap));
+    if (S.dense.nct == 1)
+      hipLaunchKernelGGL((k_union_f64<OutT, 1>), gu, dim3(kUnionBlock), lds, stream, S.dense, Cd,
+                         p0, p1, z, s, G, logscale, flags, units);
+    else
+      hipLaunchKernelGGL((k_union_f64<OutT, 2>), gu, dim3(kUnionBlock), lds, stream, S.dense, Cd,
+                         p0, p1, z, s, G, logscale, flags, units);
+  } else if (S.dense.nct == 1)
+    hipLaunchKernelGGL((k_dense_f64<OutT, 1>), grid, block, 0, stream, S.dense, Cd, p0, p1, z, s,
+                       G, logscale, flags, units);
+  else
+    hipLaunchKernelGGL((k_dense_f64<OutT, 2>), grid, block, 0, stream, S.dense, Cd, p0, p1, z, s,
+                       G, logscale, flags, units);
+  prof_end(stream, engine == 1 ? "k_dense<bf16x3>"
+                               : (S.union_support ? "k_union<fp64>" : "k_dense<fp64>"));
 }
 
 hipError_t launch_dense_eval(const System &S, const double *c, int64_t P, const double *z,

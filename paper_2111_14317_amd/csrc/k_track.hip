@@ -16,7 +16,9 @@
 //              step doubles (up to ds_max) when it took at most one correction;
 //              otherwise apply dN while k < max_newton and ||dN|| contracts by 1/2, else reject;
 //   reject   : ds /= 2 (fail below ds_min) and predict again from the last accepted point;
-//   predict  : z = z_a + h dE_a, s = s_a + h, h = min(ds, -s_a);
+//   predict  : z = z_a + h dE_a, s = s_a + h, h = min(ds, -s_a) (Euler); or, with the Hermite
+//              predictor, the cubic through the last two accepted points and their Euler
+//              directions (when h <= 4 (s_a - s_p); the first step after a claim is Euler);
 //   endgame  : at s = 0 Newton until ||dN|| <= tol_end (1 + ||z||), max_end iterations, or the
 //              step stops contracting; OK when the relative residual <= res_tol.
 // The CPU oracle runs the same rules with the same constants.
@@ -59,10 +61,10 @@ constexpr double kMixedMinStep = 1e-6;
 constexpr int kParked = 3;     // re-tracked in FP64 from its last accepted point
 constexpr int kParkedEnd = 4;  // at s = 0: only its endgame is left
 
-// LDS of the tracker's lane groups: 5 N complex values per group.
+// LDS of the tracker's lane groups: 7 N complex values per group.
 template <int N>
 __host__ __device__ constexpr size_t track_state_bytes() {
-  return (size_t)(kTrackBlock / 64) * Geo<N>::G * 5 * N * sizeof(Cx<double>);
+  return (size_t)(kTrackBlock / 64) * Geo<N>::G * 7 * N * sizeof(Cx<double>);
 }
 
 // The group's current point, read from LDS into registers for one evaluation (so the replicas are
@@ -103,15 +105,18 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
   // per-group state in LDS: accepted point, Euler direction there, current dE and dN, current
   // point (each lane keeps its own coordinate in registers and writes it here)
   const int slot = (threadIdx.x >> 6) * Geo<N>::G + (geo.valid ? geo.g : 0);
-  Cx<double> *sZa = slot_state + slot * 5 * N;
+  Cx<double> *sZa = slot_state + slot * 7 * N;
   Cx<double> *sEa = sZa + N;
   Cx<double> *sEc = sZa + 2 * N;
   Cx<double> *sNc = sZa + 3 * N;
   Cx<double> *sZc = sZa + 4 * N;
+  Cx<double> *sZp = sZa + 5 * N;  // the accepted point before (z_a, s_a), and its Euler direction
+  Cx<double> *sEp = sZa + 6 * N;  // (the Hermite predictor's second point)
   const int64_t P = p_end - p_begin;
 
   double zo_r = 0.0, zo_i = 0.0;  // this lane's own coordinate z_r of the current point
-  double sc = 0.0, sa = 0.0, ds = 0.0, nrm_prev = 0.0;
+  double sc = 0.0, sa = 0.0, ds = 0.0, nrm_prev = 0.0, sp = 0.0;
+  bool have_p = false;  // (sZp, sEp, sp) hold an accepted point before (sZa, sEa, sa)
   int64_t path = -1;
   int phase = PH_POLISH, k = 0, steps_here = 0, iters = 0;
   bool need_exact = true;  // next evaluation recomputes the row maximum (fresh path, lost lag)
@@ -130,6 +135,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     sc = s[p];
     sa = sc;
     ds = fresh ? pr.ds0 : ds_io[p];
+    have_p = false;
     phase = fresh ? PH_POLISH : (endgame ? PH_END : PH_RESUME);
     k = 0;
     steps_here = 0;
@@ -360,6 +366,14 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
           ++c0;
           ++steps_here;
           if (k <= 1) ds = fmin(2.0 * ds, pr.ds_max);
+          // the accepted point so far becomes the Hermite predictor's earlier point (each lane
+          // moves its own coordinate)
+          sZp[r] = sZa[r];
+          sEp[r] = sEa[r];
+          sp = sa;
+          have_p = true;
+        } else {
+          have_p = false;  // a path's first accepted point in this call
         }
         sZa[r] = Cx<double>{zo_r, zo_i};
         sEa[r] = e;
@@ -422,13 +436,25 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       }
       if (act == ACT_PREDICT) {
         const double hstep = fmin(ds, -sa);
+        const double st = (hstep == -sa) ? 0.0 : sa + hstep;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (geo.valid) {
           const Cx<double> za = sZa[r], ea = sEa[r];
-          zo_r = fma(hstep, ea.x, za.x);
-          zo_i = fma(hstep, ea.y, za.y);
+          if (pr.predictor == HOM_PREDICT_HERMITE && have_p && hstep <= 4.0 * (sa - sp)) {
+            // the cubic through (sp, z_p) and (sa, z_a) with slopes e_p, e_a (Sec. 2.3's
+            // Hermite predictor from the Euler directions already computed), at st
+            const Cx<double> zp = sZp[r], ep = sEp[r];
+            const double d = sa - sp, t = (st - sp) / d, t2 = t * t, t3 = t2 * t;
+            const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0, h10 = (t3 - 2.0 * t2 + t) * d;
+            const double h01 = -2.0 * t3 + 3.0 * t2, h11 = (t3 - t2) * d;
+            zo_r = h00 * zp.x + h10 * ep.x + h01 * za.x + h11 * ea.x;
+            zo_i = h00 * zp.y + h10 * ep.y + h01 * za.y + h11 * ea.y;
+          } else {
+            zo_r = fma(hstep, ea.x, za.x);
+            zo_i = fma(hstep, ea.y, za.y);
+          }
         }
-        sc = (hstep == -sa) ? 0.0 : sa + hstep;
+        sc = st;
         k = 0;
         phase = PH_TRACK;
       }
@@ -607,7 +633,7 @@ hipError_t launch_fill_i64(long long *p, long long v, int64_t n, hipStream_t str
 // ------------------------------------------------------------------------------------------
 // Batched form: many systems of uneven n and support sizes in one persistent launch.
 // ------------------------------------------------------------------------------------------
-constexpr size_t kBatchStateBytes = 20 * 1024;  // >= track_state_bytes<N>() for every N
+constexpr size_t kBatchStateBytes = 28 * 1024;  // >= track_state_bytes<N>() for every N
 static_assert(track_state_bytes<2>() <= kBatchStateBytes && track_state_bytes<3>() <= kBatchStateBytes &&
                   track_state_bytes<5>() <= kBatchStateBytes && track_state_bytes<7>() <= kBatchStateBytes,
               "batch LDS state budget");

@@ -37,7 +37,7 @@ def cond_inf(sys, c, z, s):
 def torch_params(hom, p_oracle, precision):
     """library params with the oracle's constants"""
     kw = {f: getattr(p_oracle, f) for f in ("ds0", "ds_max", "ds_min", "tol_polish", "tol_track",
-                                            "tol_end", "res_tol", "div_re", "sing_ratio", "tol_predict", "max_polish",
+                                            "tol_end", "res_tol", "div_re", "sing_ratio", "tol_predict", "predictor", "max_polish",
                                             "max_newton", "max_end", "max_steps", "max_iters")}
     return hom.default_params(precision, **kw)
 
@@ -194,3 +194,28 @@ def proj_kappa(sys_, y, s):
     J[:, n, :] = np.conj(np.concatenate([x, np.ones((len(y), 1))], axis=1))
     J /= np.abs(J).sum(2, keepdims=True)
     return np.linalg.cond(J, p=np.inf)
+
+
+def dir_err(a, b):
+    """per-point max-norm relative error of directions"""
+    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-300)
+
+
+def check_dirs(dE, dN, oE, oN, ost, kappa, mixed, n, label="", min_well=0):
+    """Every nonsingular point within the LU's forward-error bound dir_bound (kappa times 16 n u,
+    u the unit roundoff of the solve's precision; points whose FP32 pivot ratio is below 1e-4 are
+    redone in FP64 by the mixed form), and the well-conditioned ones (kappa <= 1e3 in FP64, 1e2
+    mixed) within 1e-12 / 1e-5; at least `min_well` of them.  Dense n >= 20 Jacobians at random
+    points rarely have kappa <= 1e2."""
+    kappa = np.abs(np.asarray(kappa))
+    fin = (ost == 0) & np.isfinite(kappa)
+    e = np.maximum(dir_err(dE, oE), dir_err(dN, oN))
+    tol, kmax, u = (1e-5, 1e2, 2.0 ** -24) if mixed else (1e-12, 1e3, 2.0 ** -53)
+    well = (kappa <= kmax) & fin
+    bound = dir_bound(kappa, n, u, tol)
+    say(f"  {label} kappa<={kmax:g}: {well.sum()}/{len(e)} max err {e[well].max(initial=0):.3e}; "
+        f"all {fin.sum()}: max err/bound {(e / bound)[fin].max(initial=0):.2e}, "
+        f"max err/kappa {(e / np.maximum(kappa, 1))[fin].max(initial=0):.2e}")
+    assert well.sum() >= min_well
+    assert e[well].max(initial=0.0) <= tol
+    assert (e[fin] <= bound[fin]).all()

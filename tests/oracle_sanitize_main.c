@@ -71,7 +71,7 @@ static int run(int n, int mk, int P, int threads, int track) {
     bad |= oracle_endpoint_grad(n, m, A, w, c, P, z, gx, gc) < 0;
     if (track) { /* short budgets: exercise every phase without waiting for convergence */
         const double dp[10] = {0.05, 0.5, 1e-10, 1e-12, 1e-8, 1e-14, 1e-10, 40.0, 1e-14, 1e-2};
-        const int32_t ip[5] = {10, 3, 8, 50, 200};
+        const int32_t ip[6] = {10, 3, 8, 50, 200, 1};
         for (int p = 0; p < P; p++) st[p] = 1;
         bad |= oracle_track(n, m, A, w, c, P, z, s, ds, dp, ip, st, cnt, threads) != 0;
     }

@@ -42,7 +42,7 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.hom_create(2, P(m), P(A), P(bad_w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
     bad_A = A.copy(); bad_A[0, 0] = -128
     assert lib.hom_create(2, P(m), P(bad_A), P(w), 0, ctypes.byref(out)) == hom.HOM_EINVAL
-    assert lib.hom_create(2, P(m), P(A), P(w), 4, ctypes.byref(out)) == hom.HOM_EINVAL
+    assert lib.hom_create(2, P(m), P(A), P(w), 8, ctypes.byref(out)) == hom.HOM_EINVAL
     # projective handles: n <= 29 and homogenising exponents <= 127 (checked before the GPU)
     m30 = np.full(30, 1, np.int32)
     A30 = np.zeros((30, 30), np.int8)
@@ -70,6 +70,7 @@ def test_default_params_match_oracle_defaults():
     p = hom.default_params(hom.FP64)
     o = oracle.TrackParams()
     for f in ("ds0", "ds_max", "ds_min", "tol_polish", "tol_track", "tol_end", "res_tol", "div_re",
-              "sing_ratio", "tol_predict", "max_polish", "max_newton", "max_end", "max_steps",
+              "sing_ratio", "tol_predict", "predictor", "max_polish", "max_newton", "max_end",
+              "max_steps",
               "max_iters"):
         assert getattr(p, f) == getattr(o, f), f

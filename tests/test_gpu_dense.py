@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import dir_bound, cond_inf, eval_err, eval_err_fp32, say
+from gpu_util import check_dirs as _check_dirs, dir_err as _dir_err, cond_inf, eval_err, eval_err_fp32, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,30 +21,6 @@ def hom():
 
 def _np(t):
     return t.cpu().numpy()
-
-
-def _dir_err(a, b):
-    return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-300)
-
-
-def _check_dirs(dE, dN, oE, oN, ost, kappa, mixed, n, label="", min_well=0):
-    """Every nonsingular point within the LU's forward-error bound dir_bound (kappa times 16 n u,
-    u the unit roundoff of the solve's precision; points whose FP32 pivot ratio is below 1e-4 are
-    redone in FP64 by the mixed form), and the well-conditioned ones (kappa <= 1e3 in FP64, 1e2
-    mixed) within 1e-12 / 1e-5; at least `min_well` of them.  Dense n >= 20 Jacobians at random
-    points rarely have kappa <= 1e2."""
-    kappa = np.abs(np.asarray(kappa))
-    fin = (ost == 0) & np.isfinite(kappa)
-    e = np.maximum(_dir_err(dE, oE), _dir_err(dN, oN))
-    tol, kmax, u = (1e-5, 1e2, 2.0 ** -24) if mixed else (1e-12, 1e3, 2.0 ** -53)
-    well = (kappa <= kmax) & fin
-    bound = dir_bound(kappa, n, u, tol)
-    say(f"  {label} kappa<={kmax:g}: {well.sum()}/{len(e)} max err {e[well].max(initial=0):.3e}; "
-        f"all {fin.sum()}: max err/bound {(e / bound)[fin].max(initial=0):.2e}, "
-        f"max err/kappa {(e / np.maximum(kappa, 1))[fin].max(initial=0):.2e}")
-    assert well.sum() >= min_well
-    assert e[well].max(initial=0.0) <= tol
-    assert (e[fin] <= bound[fin]).all()
 
 
 def _ragged(seed=11, n=20, lift=12):

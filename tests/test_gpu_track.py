@@ -184,3 +184,25 @@ def test_every_group_size(hom, n):
     check_fp64_per_path(csys, _np(a.z), _np(a.status), ze, ost, "fp64")
     b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
     check_mixed_set(csys, _np(b.z), _np(b.status), ze, ost, "mixed", min_ok=1.0)
+
+
+@pytest.mark.parametrize("cfg,P", [("c5", 2048), ("c2", 16384)])
+def test_hermite_predictor_matches_oracle(hom, cfg, P):
+    """The cubic Hermite predictor (from the last two accepted points and their Euler
+    directions): FP64 path by path against the oracle's tracker with the same predictor, the mixed
+    form path by path as well, both with fewer eval+solves than the Euler predictor."""
+    say(f"[track hermite] {cfg} P={P}")
+    csys, cell, z0 = W.planted_config(cfg, P=P)
+    h = hom.System.from_workload(csys)
+    po = oracle.TrackParams(predictor=1)
+    ze, _, _, ost, ocnt = oracle.track(csys, csys.c, z0, -32.0, po)
+    a = hom.track(h, csys.c, z0, -32.0, torch_params(hom, po, hom.FP64))
+    check_fp64_per_path(csys, _np(a.z), _np(a.status), ze, ost, "fp64 hermite")
+    gc = _np(a.counters)
+    assert abs(gc[:, 3].mean() / ocnt[:, 3].mean() - 1) < 0.02
+    b = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED, predictor=hom.PREDICT_HERMITE))
+    check_mixed_set(csys, _np(b.z), _np(b.status), ze, ost, "mixed hermite", max_swaps=0.0)
+    e = hom.track(h, csys.c, z0, -32.0, hom.default_params(hom.MIXED))
+    say(f"  eval+solves per path: hermite {_np(b.counters)[:, 3].mean():.1f}, "
+        f"euler {_np(e.counters)[:, 3].mean():.1f} (mixed); fp64 hermite {gc[:, 3].mean():.1f}")
+    assert _np(b.counters)[:, 3].mean() < _np(e.counters)[:, 3].mean()

@@ -1,0 +1,114 @@
+"""GPU parity of the common-support engine (the unmixed case of Sec. 5.1: the exponentials formed
+once per point and shared by all equations) against the oracle, which evaluates every equation
+from its definition."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import check_dirs, cond_inf, eval_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hom():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2111_14317_amd as hom
+    return hom
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _engines(hom, h, call):
+    hom.profile_read()
+    hom.set_profiling(True)
+    out = call()
+    import torch
+    torch.cuda.synchronize()
+    hom.set_profiling(False)
+    return out, {name for name, _, _ in hom.profile_read()}
+
+
+@pytest.mark.parametrize("n,m,P", [(32, 128, 200), (20, 50, 37), (6, 33, 1), (32, 256, 64)])
+def test_union_eval_vs_oracle(hom, n, m, P):
+    """Common supports (m = 50, 33 pad to 64; 256 is the largest): the shared-exponential engine
+    against the oracle (componentwise scaled error <= 1e-12); one shift per point, within 0.25 of
+    every row maximum's largest."""
+    say(f"[union eval] n={n} m={m} P={P}")
+    sys_, z, s = W.union_config(P=P, n=n, m=m)
+    h = hom.System.from_workload(sys_)
+    (G, L), eng = _engines(hom, h, lambda: hom.eval(h, sys_.c, z, s))
+    assert "k_union<fp64>" in eng, eng
+    Go, Lo, den = oracle.eval(sys_, sys_.c, z, s, with_den=True)
+    G, L = _np(G), _np(L)
+    err = eval_err(G, L, Go, Lo, den)
+    say(f"  max scaled err {err.max():.3e}")
+    assert np.isfinite(G).all() and err.max() <= 1e-12
+    assert (L == L[:, :1]).all()
+    assert np.abs(L[:, 0] - Lo.max(1)).max() <= 0.25
+
+
+def test_union_detection_and_per_equation_handle(hom):
+    """A system whose equations differ in one lifting is evaluated per equation; a common-support
+    system created with per_equation=True too; both agree with the oracle."""
+    say("[union] detection")
+    sys_, z, s = W.union_config(P=50, n=12, m=40)
+    Go, Lo, den = oracle.eval(sys_, sys_.c, z, s, with_den=True)
+    h = hom.System.from_workload(sys_, per_equation=True)
+    (G, L), eng = _engines(hom, h, lambda: hom.eval(h, sys_.c, z, s))
+    assert "k_dense<fp64>" in eng and "k_union<fp64>" not in eng
+    assert eval_err(_np(G), _np(L), Go, Lo, den).max() <= 1e-12
+    w2 = sys_.w.copy()
+    w2[40 * 5 + 7] += 1.0  # equation 5, monomial 7
+    s2 = W.System(sys_.n, sys_.m, sys_.A, w2, sys_.c)
+    h2 = hom.System.from_workload(s2)
+    (G2, L2), eng2 = _engines(hom, h2, lambda: hom.eval(h2, s2.c, z, s))
+    assert "k_union<fp64>" not in eng2
+    Go2, Lo2, den2 = oracle.eval(s2, s2.c, z, s, with_den=True)
+    assert eval_err(_np(G2), _np(L2), Go2, Lo2, den2).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_union_step_vs_oracle(hom, prec):
+    """The step on common-support handles (shared-exponential evaluation, then the LU): at
+    n = 32, m = 128 every nonsingular point within the LU's forward-error bound (random points of
+    this system all have kappa > 1e3); at n = 8, m = 40 at least 100 points within 1e-12 (FP64,
+    kappa <= 1e3; 204 of the 512 points) or 10 within 1e-5 (mixed, kappa <= 1e2; 16 points)."""
+    precision = hom.FP64 if prec == "fp64" else hom.MIXED
+    rng = np.random.default_rng(41)
+    small = W.union_system(8, 40, W._uniform_exps(-2, 2), "unit", 15, rng, rng, rng)
+    zs, ss = W.random_points(8, 512, rng, s_lo=-2.0)
+    for (sys_, z, s), min_well in ((W.union_config(P=300), 0),
+                                   ((small, zs, ss), 100 if prec == "fp64" else 10)):
+        say(f"[union step] {prec} n={sys_.n} m={int(sys_.m[0])} P={len(s)}")
+        h = hom.System.from_workload(sys_)
+        dE, dN, st = hom.step(h, sys_.c, z, s, precision=precision)
+        oE, oN, ost, ratio = oracle.step(sys_, sys_.c, z, s)
+        kappa = cond_inf(sys_, sys_.c, z, s)
+        check_dirs(_np(dE), _np(dN), oE, oN, ost, kappa, prec == "mixed", sys_.n,
+                   min_well=min_well)
+        if prec == "fp64":
+            assert np.array_equal(_np(st) == 0, (ost == 0) & (ratio >= 1e-14))
+
+
+def test_union_full_size_sampled(hom):
+    """262144 points of the common-support n = 32, m = 128 system; 128 sampled points against the
+    oracle."""
+    import torch
+    say("[union full] P=262144 sampled")
+    sys_, z, s = W.union_config()
+    h = hom.System.from_workload(sys_)
+    idx = np.random.default_rng(6).choice(len(s), 128, replace=False)
+    Go, Lo, den = oracle.eval(sys_, sys_.c, z[idx], s[idx], with_den=True)
+    G, L = hom.eval(h, sys_.c, z, s)
+    ti = torch.as_tensor(idx, device="cuda")
+    Gs, Ls = _np(G[ti]), _np(L[ti])
+    del G, L
+    torch.cuda.empty_cache()
+    err = eval_err(Gs, Ls, Go, Lo, den)
+    say(f"  max scaled err {err.max():.3e}")
+    assert err.max() <= 1e-12

@@ -159,3 +159,66 @@ def test_failure_modes_forced():
     assert (st[2:] == oracle.OK).all()
     z, s, ds, st, cnt = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(max_steps=0))
     assert (st == oracle.RUNNING).all() and (s == -32.0).all()
+
+
+# ---- the cubic Hermite predictor (Sec. 2.3: predictors built on the Euler direction) -----------
+def test_hermite_predictor_matches_scipy():
+    """The tracker's predictor against scipy's CubicHermiteSpline (extrapolating past s1), real
+    and imaginary parts separately."""
+    from scipy.interpolate import CubicHermiteSpline
+    rng = np.random.default_rng(3)
+    P, n = 50, 4
+    s0 = rng.uniform(-10, -1, P)
+    s1 = s0 + rng.uniform(0.01, 0.7, P)
+    s = s1 + (s1 - s0) * rng.uniform(0.0, 3.0, P)
+    z0, z1, e0, e1 = (rng.normal(size=(P, n)) + 1j * rng.normal(size=(P, n)) for _ in range(4))
+    got = oracle.hermite(s0, z0, e0, s1, z1, e1, s)
+    for p in range(P):
+        for part in (np.real, np.imag):
+            sp = CubicHermiteSpline([s0[p], s1[p]], np.stack([part(z0[p]), part(z1[p])]),
+                                    np.stack([part(e0[p]), part(e1[p])]), extrapolate=True)
+            np.testing.assert_allclose(part(got[p]), sp(s[p]), rtol=1e-12, atol=1e-12)
+
+
+def test_hermite_predictor_exact_on_cubics():
+    """A cubic path is reproduced exactly from two points and their slopes, at any s."""
+    rng = np.random.default_rng(4)
+    P, n = 40, 3
+    a = [rng.normal(size=(P, n)) + 1j * rng.normal(size=(P, n)) for _ in range(4)]
+
+    def z(s):
+        return a[0] + a[1] * s[:, None] + a[2] * s[:, None] ** 2 + a[3] * s[:, None] ** 3
+
+    def dz(s):
+        return a[1] + 2 * a[2] * s[:, None] + 3 * a[3] * s[:, None] ** 2
+
+    s0 = rng.uniform(-3, -1, P)
+    s1 = s0 + rng.uniform(0.1, 0.5, P)
+    s = s1 + rng.uniform(0.0, 1.0, P)
+    got = oracle.hermite(s0, z(s0), dz(s0), s1, z(s1), dz(s1), s)
+    np.testing.assert_allclose(got, z(s), rtol=1e-10, atol=1e-10)
+
+
+def test_hermite_tracker_same_roots():
+    """Tracking with the Hermite predictor ends every path on the Euler predictor's endpoint
+    (path by path; the c1 cells and 300 n = 8 planted-cell paths), with fewer eval+solves."""
+    base, cells = W.c1_cells()
+    ev = {0: 0, 1: 0}
+    for csys, info, z0 in cells:
+        res = {}
+        for pred in (0, 1):
+            ze, _, _, st, cnt = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=pred))
+            assert (st == oracle.OK).all()
+            res[pred] = ze
+            ev[pred] += int(cnt[:, 3].sum())
+        d = np.abs(res[0] - res[1])
+        d = np.maximum(np.abs(d.real), np.abs(np.angle(np.exp(1j * (res[0].imag - res[1].imag)))))
+        assert d.max() <= 1e-12
+    csys, cell, z0 = W.planted_config("c5", P=300)
+    a = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=0))
+    b = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=1))
+    assert (a[3] == 0).all() and (b[3] == 0).all()
+    dre = np.abs(a[0].real - b[0].real).max(1)
+    dim = np.abs(np.angle(np.exp(1j * (a[0].imag - b[0].imag)))).max(1)
+    assert np.maximum(dre, dim).max() <= 1e-12
+    assert b[4][:, 3].sum() < a[4][:, 3].sum() and ev[1] < ev[0]

@@ -113,6 +113,29 @@ def random_system(n, m, draw_exps, coef_kind, lift_hi, rng_sup, rng_coef, rng_li
     return System(n, m, A, w, c)
 
 
+def union_system(n, m, draw_exps, coef_kind, lift_hi, rng_sup, rng_coef, rng_lift) -> System:
+    """A system with one common support (the unmixed case of Sec. 5.1): m distinct exponent
+    vectors and their liftings shared by every equation (listed in the same order), and an
+    independent coefficient for every (equation, monomial)."""
+    rows = _distinct_rows(rng_sup, m, n, draw_exps)
+    S = np.array(rows, dtype=np.int8).reshape(m, n)
+    w = rng_lift.integers(0, lift_hi + 1, size=m).astype(np.float64)
+    A = np.tile(S, (n, 1))
+    c = _coefficients(rng_coef, n * m, coef_kind)
+    return System(n, np.full(n, m, np.int32), A, np.tile(w, n), c)
+
+
+def union_config(P: int | None = None, n: int = 32, m: int = 128):
+    """The dense configuration's shapes (exponents in [-4, 4] with 30% zeros, complex Gaussian
+    coefficients, liftings U{0..255}, points as the other configurations) with one support common
+    to all equations; P = 262144 by default."""
+    r_sup, r_coef, r_lift, r_pts, _, _ = streams("c3")
+    r_sup = np.random.default_rng(r_sup.integers(2 ** 63))  # a stream of its own
+    sys = union_system(n, m, _sparse_exps(4, 0.3), "gauss", 255, r_sup, r_coef, r_lift)
+    z, s = random_points(n, 262144 if P is None else P, r_pts)
+    return sys, z, s
+
+
 def random_points(n, P, rng, s_lo=-8.0, s_hi=0.0):
     """Re z ~ N(0, 0.5), Im z ~ U[0, 2 pi), s ~ U[s_lo, s_hi]."""
     z = rng.normal(0.0, 0.5, size=(P, n)) + 1j * rng.uniform(0.0, 2.0 * np.pi, size=(P, n))
