@@ -19,6 +19,9 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   residual        pinned: hand-worked exact values (tests/golden/residual_2x2.json), exact
                   rational arithmetic at rational points, the closed form at perturbed binomial
                   roots, zeros at roots, coefficient-scale and branch invariance
+  binomial_roots  (oracle/binomial.py, Python) pinned: every root's residual from the
+                  definition, |det D| pairwise distinct roots, closed forms for n = 1 and diagonal
+                  D, equation-order invariance, the input generator's Smith-form roots
 """
 from __future__ import annotations
 
@@ -245,3 +248,6 @@ def endpoint_grad(sys, c, z_end, grad_x):
     ns = _checked(lib.oracle_endpoint_grad(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), z.shape[0],
                                            _ptr(z), _ptr(g), _ptr(out)))
     return out, int(ns)
+
+
+from .binomial import binomial_roots  # noqa: E402  (plain Python; no C)
