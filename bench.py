@@ -341,6 +341,36 @@ def run_union(hom, torch, P, reps=3):
     return out
 
 
+def run_starts(hom, torch, reps=3):
+    """Start points of the n = 10 tracking workload's planted cell: all |det D| = 3,881,632 roots
+    of its binomial system (host Smith form, then one GPU launch writing 16 bytes per root
+    coordinate, judged against HBM)."""
+    import workloads as W
+    csys, cell, _ = W.planted_config("c2", P=4)
+    D, beta = W.cell_binomial(csys, cell)
+    z, num = hom.binomial_starts(D, beta)
+    del z
+    torch.cuda.synchronize()
+    hom.profile_read()
+    hom.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        z, _ = hom.binomial_starts(D, beta)
+        del z
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    hom.set_profiling(False)
+    ms = sum(t for k, t, _ in hom.profile_read() if k == "k_binomial_starts") / reps
+    rows = int(num[0])
+    nbytes = rows * csys.n * 16
+    rec = {"roots": rows, "n": csys.n, "kernel_ms": ms, "call_ms": wall * 1e3,
+           "roots_per_s": rows / (ms * 1e-3), "hbm_gb_per_s": nbytes / (ms * 1e-3) / 1e9,
+           "frac_of_hbm_peak": nbytes / (ms * 1e-3) / PEAK_HBM}
+    print(f"# starts n=10 cell: {rows} roots, kernel {ms:.3f} ms ({rec['hbm_gb_per_s']:.0f} GB/s), "
+          f"call {wall * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    return rec
+
+
 def run_eval_n10(hom, torch, P=65536, reps=5):
     """hom_eval and hom_step on P random points of the n = 10 system.  The evaluation reads z, s and
     writes G and the row scales (2168 B per point at n = 10): it is judged against HBM bandwidth."""
@@ -759,6 +789,7 @@ def main():
         out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)
         out["dense_n32_m128"] = run_dense(hom, torch, args.dense_points)
         out["common_support_n32_m128"] = run_union(hom, torch, args.dense_points)
+        out["start_points_n10_cell"] = run_starts(hom, torch)
         out["step_proj_n10_65536_points"] = run_step_proj(hom, torch)
     if not args.no_batch:
         out["batch_c4"] = run_c4(hom, torch)

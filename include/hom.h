@@ -293,6 +293,31 @@ int hom_endpoint_grad(hom_system_t sys, const double *c, int64_t P, const double
                       const double *grad_x, double *grad_c, int precision, hom_stream_t stream);
 
 /*
+ * Start points (Sec. 2): the paths of polyhedral homotopy start at the roots of each mixed cell's
+ * binomial system x^{d_k} = beta_k, k = 0..n-1 (d_k = the difference of the cell's two exponent
+ * vectors in equation k, beta_k = -c_{k,j0} / c_{k,j1}); the paper takes them as given.  This
+ * writes them, for any number of cells of one size n, in log coordinates z = log x.
+ *   D      host int32 [num_cells][n][n], row k of cell c = d_k (nonsingular).
+ *   beta   host complex [num_cells][n] (interleaved re, im), finite and nonzero.
+ *   first, count   host int64 [num_cells] or both NULL: cell c's roots with index q in
+ *          [first[c], first[c] + count[c]) (NULL: all of them, 0 .. |det D_c| - 1).  Root q of a
+ *          cell is the one whose mixed-radix digits over the Smith invariant factors of D that
+ *          exceed one (the first factor's digit varying fastest) are j: z = z_base + 2 pi i
+ *          V S^{-1} j with z_base = D^{-1} log(beta) (principal logarithm), U D V = S.
+ *   num_roots  host int64 [num_cells], out: |det D_c|, the number of roots of cell c.
+ *   z      device complex [z_rows][n] or NULL: the roots, cell after cell; Im z in [-pi, pi).
+ *          NULL: only num_roots is computed (nothing touches the GPU).
+ * n in [1, 32]; |det D_c| < 2^62 and its largest invariant factor < 2^31 (HOM_EUNSUPPORTED
+ * otherwise).  Blocks until its per-cell tables are on the device; the roots are written
+ * asynchronously on `stream`.
+ * Errors: HOM_EINVAL (bad argument, singular D, zero or non-finite beta, a range outside
+ * [0, |det D_c|], more rows than z_rows), HOM_EUNSUPPORTED, HOM_ENOMEM, HOM_EDEVICE.
+ */
+int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *beta,
+                        const int64_t *first, const int64_t *count, int64_t *num_roots, double *z,
+                        int64_t z_rows, hom_stream_t stream);
+
+/*
  * Kernel timing (tracing).  While profiling is on for the calling thread, every kernel the
  * compute calls launch is bracketed by two hipEvents recorded on the launch stream, and the
  * tracker kernels also count the eval+solves they perform.  hom_profile_read waits for those

@@ -35,7 +35,8 @@ PREDICT_EULER, PREDICT_HERMITE = 0, 1
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_step_proj", "hom_track_params_default", "hom_track", "hom_track_noalloc",
-            "hom_endpoint_grad", "hom_set_profiling", "hom_profile_read", "hom_last_error"]
+            "hom_endpoint_grad", "hom_binomial_starts", "hom_set_profiling", "hom_profile_read",
+            "hom_last_error"]
 
 
 class HomError(RuntimeError):
@@ -78,6 +79,7 @@ def _load():
     lib.hom_track.argtypes = [P, P, i64, P, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
     lib.hom_track_noalloc.argtypes = [P, P, i64, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
     lib.hom_endpoint_grad.argtypes = [P, P, i64, P, P, P, i32, P]
+    lib.hom_binomial_starts.argtypes = [i32, i32, P, P, P, P, P, P, i64, P]
     lib.hom_set_profiling.argtypes = [i32]
     lib.hom_profile_read.argtypes = [P, P, P, i32]
     lib.hom_last_error.restype = ctypes.c_char_p
@@ -230,6 +232,39 @@ def step_proj(sys: System, c, y, s, device="cuda"):
     _check(lib.hom_step_proj(sys.handle, _ptr(c), P, _ptr(y), _ptr(s), _ptr(dE), _ptr(dN),
                              _ptr(st), _stream()))
     return dE, dN, st
+
+
+def binomial_starts(D, beta, first=None, count=None, device="cuda"):
+    """Roots of binomial start systems x^{d_k} = beta_k (Sec. 2), one system per cell:
+    D int [cells][n][n] (or [n][n]), beta complex [cells][n] (or [n]).  With first/count
+    ([cells] each) only roots first .. first + count - 1 of each cell.  Returns (z, num_roots):
+    z complex128 [rows][n] on the device (log coordinates, the cells' roots one after the
+    other), num_roots int64 [cells] = |det D| per cell."""
+    import torch
+    D = np.ascontiguousarray(D, np.int32)
+    if D.ndim == 2:
+        D = D[None]
+    cells, n = D.shape[0], D.shape[1]
+    if D.shape != (cells, n, n):
+        raise ValueError("D must be [cells][n][n]")
+    beta = np.ascontiguousarray(np.asarray(beta, np.complex128).reshape(cells, n))
+    if (first is None) != (count is None):
+        raise ValueError("first and count go together")
+    f = c = None
+    if first is not None:
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(first, np.int64), (cells,)))
+        c = np.ascontiguousarray(np.broadcast_to(np.asarray(count, np.int64), (cells,)))
+    num = np.zeros(cells, np.int64)
+    args = (n, cells, D.ctypes.data_as(ctypes.c_void_p), beta.ctypes.data_as(ctypes.c_void_p),
+            f.ctypes.data_as(ctypes.c_void_p) if f is not None else None,
+            c.ctypes.data_as(ctypes.c_void_p) if c is not None else None,
+            num.ctypes.data_as(ctypes.c_void_p))
+    _check(lib.hom_binomial_starts(*args, None, 0, None))  # sizing: num_roots only
+    rows = int(c.sum()) if c is not None else int(num.sum())
+    z = torch.empty((rows, n), dtype=torch.complex128, device=device)
+    if rows:
+        _check(lib.hom_binomial_starts(*args, _ptr(z), rows, _stream()))
+    return z, num
 
 
 @dataclasses.dataclass

@@ -281,6 +281,52 @@ extern "C" {
 
 const char *hom_last_error(void) { return g_err.c_str(); }
 
+int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *beta,
+                        const int64_t *first, const int64_t *count, int64_t *num_roots, double *z,
+                        int64_t z_rows, hom_stream_t stream) {
+  g_err.clear();
+  if (n < 1 || n > 32) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: n must be in [1, 32]");
+  if (num_cells < 1) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: num_cells < 1");
+  if (!D || !beta || !num_roots) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: NULL array");
+  if ((first == nullptr) != (count == nullptr))
+    HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: first and count must both be given or both NULL");
+  std::vector<StartPlan> plans(num_cells);
+  for (int c = 0; c < num_cells; ++c) {
+    int code = HOM_EINVAL;
+    const std::string why = start_plan(n, D + (size_t)c * n * n, beta + (size_t)c * 2 * n,
+                                       &plans[c], &code);
+    if (!why.empty())
+      HOM_FAIL(code, "hom_binomial_starts: cell " + std::to_string(c) + ": " + why);
+    num_roots[c] = plans[c].det;
+    if (first && (first[c] < 0 || count[c] < 0 || first[c] > plans[c].det ||
+                  count[c] > plans[c].det - first[c]))
+      HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: cell " + std::to_string(c) +
+                               ": [first, first + count) outside its roots");
+  }
+  if (!z) return HOM_OK;
+  std::vector<StartHdr> hdr;
+  std::vector<int64_t> data;
+  int64_t rows = 0;
+  start_pack(n, plans, first, count, hdr, data, &rows);
+  if (rows > z_rows) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: more roots than z_rows");
+  if (rows == 0) return HOM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t hb = hdr.size() * sizeof(StartHdr), db = data.size() * 8;
+  char *ws = nullptr;
+  HOM_HIP(hipMallocAsync((void **)&ws, hb + db + 8, st), "hom_binomial_starts: workspace");
+  hipError_t e = hipMemcpyAsync(ws, hdr.data(), hb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && db)
+    e = hipMemcpyAsync(ws + hb, data.data(), db, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host tables die with this call
+  if (e == hipSuccess)
+    e = launch_binomial_starts(n, num_cells, reinterpret_cast<const StartHdr *>(ws),
+                               reinterpret_cast<const int64_t *>(ws + hb), rows, z, st);
+  hipError_t e2 = hipFreeAsync(ws, st);
+  HOM_HIP(e, "hom_binomial_starts");
+  HOM_HIP(e2, "hom_binomial_starts: free workspace");
+  return HOM_OK;
+}
+
 int hom_set_profiling(int on) {
   g_err.clear();
   if (on && !g_units_pool)

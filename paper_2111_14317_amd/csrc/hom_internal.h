@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/hom.h"
 #include "hom_device.h"
@@ -170,5 +171,27 @@ hipError_t launch_step_proj(const System &S, const void *cws, const double *c, i
 
 // number of compute units of the current device (cached)
 int num_cus();
+
+// Start points (k_start.hip): one binomial cell's plan (host) and its device header.
+struct StartPlan {
+  int64_t det = 0, L = 1;       // |det D| and the largest invariant factor
+  std::vector<int64_t> sig;     // invariant factors above one
+  std::vector<int64_t> cm;      // [sig.size()][n]: (V_il mod sig_l) * (L / sig_l) mod L
+  std::vector<double> zb;       // z_base = D^{-1} log(beta), complex [n]
+};
+struct StartHdr {
+  int64_t row0;   // first output row of the cell
+  int64_t first;  // first root index
+  int64_t count;  // roots written
+  int64_t L;
+  int64_t off;    // offset of the cell's data (int64 words)
+  int32_t nlive, pad;
+};
+std::string start_plan(int n, const int32_t *D, const double *beta, StartPlan *out, int *code);
+void start_pack(int n, const std::vector<StartPlan> &plans, const int64_t *first,
+                const int64_t *count, std::vector<StartHdr> &hdr, std::vector<int64_t> &data,
+                int64_t *rows);
+hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *data,
+                                  int64_t rows, double *z, hipStream_t stream);
 
 }  // namespace hom

@@ -1,0 +1,148 @@
+"""GPU start points (Sec. 2: the roots of each mixed cell's binomial system) against the oracle:
+the whole root set of every cell, compared as sets (the two enumerate the roots in different
+orders), and at full size through properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hom():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2111_14317_amd as hom
+    return hom
+
+
+def _residual(D, beta, z):
+    return (np.abs(np.exp(z @ np.asarray(D, np.float64).T) - beta[None, :]) / np.abs(beta)).max(1)
+
+
+def _match(a, b, tol):
+    """every row of a within tol of a row of b (Im mod 2 pi), one to one"""
+    assert a.shape == b.shape
+    key = lambda z: np.round(np.concatenate([z.real, np.mod(z.imag, 2 * np.pi)], 1) * 1e6)
+    ib = {tuple(r): k for k, r in enumerate(key(b))}
+    used = np.zeros(len(b), bool)
+    worst = 0.0
+    for k, r in enumerate(key(a)):
+        j = ib.get(tuple(r))
+        if j is None:  # rounding at a key boundary: nearest by search
+            d = np.maximum(np.abs(b.real - a[k].real), np.abs(np.angle(np.exp(1j * (b.imag - a[k].imag))))).max(1)
+            j = int(d.argmin())
+        d = max(np.abs(b[j].real - a[k].real).max(), np.abs(np.angle(np.exp(1j * (b[j].imag - a[k].imag)))).max())
+        worst = max(worst, d)
+        assert not used[j], "two roots match one oracle root"
+        used[j] = True
+    assert worst <= tol, worst
+    return worst
+
+
+def _cell(rng, n, max_det):
+    """A nonsingular integer D with 1 < |det D| <= max_det and its beta: rejection sampling of
+    entries in [-3, 3] for n <= 4; above, D = L U with L unit lower triangular and U upper
+    triangular (off the diagonals, entries in [-1, 1] with density 2 / n, so that D stays well
+    conditioned; U's diagonal from {1, 2, 3}), rows and columns permuted."""
+    beta = rng.normal(size=n) + 1j * rng.normal(size=n)
+    if n <= 4:
+        while True:
+            D = rng.integers(-3, 4, size=(n, n))
+            d = round(abs(np.linalg.det(D)))
+            if 1 < d <= max_det:
+                return D, beta
+    while True:
+        diag = rng.choice([1, 1, 2, 3], size=n)
+        if 1 < np.prod(diag) <= max_det:
+            break
+    sparse = lambda: rng.integers(-1, 2, size=(n, n)) * (rng.random((n, n)) < 2.0 / n)
+    Lo = np.tril(sparse(), -1) + np.eye(n, dtype=np.int64)
+    Up = np.triu(sparse(), 1) + np.diag(diag)
+    D = (Lo @ Up)[rng.permutation(n)][:, rng.permutation(n)]
+    return D, beta
+
+
+@pytest.mark.parametrize("n,seed,max_det", [(1, 0, 40), (2, 1, 300), (3, 2, 300), (4, 3, 300),
+                                            (6, 4, 300), (10, 5, 200), (16, 6, 64), (32, 7, 48)])
+def test_cell_roots_equal_oracle_set(hom, n, seed, max_det):
+    """Every root of one cell; the set equals the oracle's to 1e-12 (Im mod 2 pi)."""
+    rng = np.random.default_rng(seed)
+    D, beta = _cell(rng, n, max_det)
+    ref = oracle.binomial_roots(D, beta)
+    say(f"[binomial] n={n} det={len(ref)}")
+    z, num = hom.binomial_starts(D, beta)
+    z = z.cpu().numpy()
+    assert num[0] == len(ref) == len(z)
+    w = _match(z, ref, 1e-12)
+    assert (z.imag >= -np.pi).all() and (z.imag < np.pi).all()
+    say(f"  max |dz| {w:.2e}")
+
+
+def test_many_cells_one_call_and_ranges(hom):
+    """200 cells of n = 5 in one launch, each cell's block against the oracle; sub-ranges equal
+    the matching rows of the full call; an empty range writes nothing."""
+    rng = np.random.default_rng(11)
+    cells = [_cell(rng, 5, 60) for _ in range(200)]
+    D = np.stack([c[0] for c in cells])
+    beta = np.stack([c[1] for c in cells])
+    say("[binomial] 200 cells n=5")
+    z, num = hom.binomial_starts(D, beta)
+    z = z.cpu().numpy()
+    assert len(z) == num.sum()
+    off = np.concatenate([[0], np.cumsum(num)])
+    for k in range(0, 200, 7):
+        _match(z[off[k]:off[k + 1]], oracle.binomial_roots(D[k], beta[k]), 1e-12)
+    first = np.minimum(num // 3, num - 1)
+    count = np.where(np.arange(200) % 5 == 0, 0, num - first)
+    zr, _ = hom.binomial_starts(D, beta, first=first, count=count)
+    zr = zr.cpu().numpy()
+    ro = np.concatenate([[0], np.cumsum(count)])
+    for k in range(200):
+        assert np.array_equal(zr[ro[k]:ro[k + 1]], z[off[k] + first[k]:off[k] + first[k] + count[k]])
+
+
+def test_planted_cell_roots_and_tracking(hom):
+    """The n = 8 planted cell (4820 roots): the GPU set equals the oracle's; all 4820 paths tracked
+    in FP64 from each side's own start points end on the same endpoint set."""
+    import torch
+    csys, cell, _ = W.planted_config("c5", P=4)
+    D, beta = W.cell_binomial(csys, cell)
+    ref = oracle.binomial_roots(D, beta)
+    say(f"[binomial] planted n=8 cell, {len(ref)} roots")
+    z, num = hom.binomial_starts(D, beta)
+    _match(z.cpu().numpy(), ref, 1e-12)
+    h = hom.System.from_workload(csys)
+    st = hom.track(h, csys.c, z, -32.0, hom.default_params(hom.FP64))
+    ze = st.z.cpu().numpy()
+    assert (st.status.cpu().numpy() == 0).all()
+    zo, _, _, sto, _ = oracle.track(csys, csys.c, ref, -32.0, oracle.TrackParams())
+    assert (sto == 0).all()
+    _match(ze, zo, 1e-10)
+
+
+def test_full_size_cell_properties(hom):
+    """All 3,881,632 roots of the n = 10 planted cell (the tracking benchmark's start system):
+    sampled roots satisfy the system (relative 1e-12 from the definition), and the roots are
+    pairwise distinct (their lattice points 2 pi Im(z - z_0) L are distinct integer vectors)."""
+    import torch
+    csys, cell, _ = W.planted_config("c2", P=4)
+    D, beta = W.cell_binomial(csys, cell)
+    say("[binomial] n=10 cell, all roots")
+    z, num = hom.binomial_starts(D, beta)
+    assert len(z) == num[0] == 3881632
+    idx = np.random.default_rng(3).choice(len(z), 4096, replace=False)
+    zs = z[torch.as_tensor(idx, device=z.device)].cpu().numpy()
+    assert _residual(D, beta, zs).max() <= 1e-12
+    zn = z.cpu().numpy()
+    del z
+    torch.cuda.empty_cache()
+    assert (zn.imag >= -np.pi).all() and (zn.imag < np.pi).all()
+    assert np.abs(zn.real - zn[:1].real).max() <= 1e-12  # Re z is the same for every root
+    U, sig, V = W.smith_normal_form(D)
+    L = int(sig[-1])
+    lat = np.mod(np.rint((zn.imag - zn[:1].imag) / (2 * np.pi) * L).astype(np.int64), L)
+    assert len(np.unique(lat, axis=0)) == len(zn)
