@@ -11,7 +11,8 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
                   branch invariance, J_x = J_z diag(e^{-z}), zeros at binomial roots
   step            pinned: LAPACK solve, Cramer's rule, closed-form directions of binomial systems
   track           pinned: closed-form binomial paths, mixed-volume root count, residuals; the
-                  Hermite predictor against scipy's CubicHermiteSpline and exactness on cubics
+                  Hermite predictor against scipy's CubicHermiteSpline and exactness on cubics;
+                  the Runge-Kutta predictor's fourth order on a closed-form trinomial path
   endpoint_grad   pinned: central finite differences of re-solved endpoints
   step_proj       pinned: homogeneity of degree one under y -> lambda y, the affine directions
                   mapped into homogeneous coordinates (from the affine evaluation and numpy
@@ -69,6 +70,8 @@ def _load():
         _lib.oracle_step_proj.argtypes = [i32, P, P, P, P, i64, P, P, P, P, P, P, P, i32]
         _lib.oracle_hermite.argtypes = [i32, i64, P, P, P, P, P, P, P, P]
         _lib.oracle_hermite.restype = i32
+        _lib.oracle_rk4_predict.argtypes = [i32, P, P, P, P, i64, P, P, P, P]
+        _lib.oracle_rk4_predict.restype = i32
         for name in ("oracle_eval", "oracle_step", "oracle_track", "oracle_residual",
                      "oracle_endpoint_grad", "oracle_step_proj"):
             getattr(_lib, name).restype = i32
@@ -149,6 +152,23 @@ def hermite(s0, z0, e0, s1, z1, e1, s):
     return out
 
 
+def rk4_predict(sys, c, za, sa, h):
+    """The tracker's Runge-Kutta predictor from points za [P][n] at sa [P] with steps h [P]
+    (the classical fourth-order scheme on dz/ds = dE(z, s)); NaN rows where a stage point is
+    singular."""
+    lib = _load()
+    m, A, w = _sys_arrays(sys)
+    za = np.ascontiguousarray(za, np.complex128)
+    P = za.shape[0]
+    sa = np.ascontiguousarray(np.broadcast_to(np.asarray(sa, np.float64), (P,)))
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (P,)))
+    c = np.ascontiguousarray(c, np.complex128)
+    out = np.zeros_like(za)
+    _checked(lib.oracle_rk4_predict(sys.n, _ptr(m), _ptr(A), _ptr(w), _ptr(c), P, _ptr(za),
+                                    _ptr(sa), _ptr(h), _ptr(out)))
+    return out
+
+
 def step_proj(sys, c, y, s, threads=None):
     """Euler and Newton directions in homogeneous coordinates (Sec. 2.2, eq. (3)-(5)) at points
     y [P][n+1] (y_j pairs with x_j for j < n; y_n is the homogenising coordinate, so an affine
@@ -193,7 +213,8 @@ class TrackParams:
     max_end: int = 8
     max_steps: int = 100000
     max_iters: int = 100000
-    predictor: int = 0  # 0 Euler, 1 cubic Hermite through the last two accepted points
+    predictor: int = 0  # 0 Euler, 1 cubic Hermite through the last two accepted points,
+    #                     2 classical Runge-Kutta (three more evaluations per step)
 
     def arrays(self):
         d = np.array([self.ds0, self.ds_max, self.ds_min, self.tol_polish, self.tol_track,

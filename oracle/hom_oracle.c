@@ -383,7 +383,8 @@ typedef struct {
     double sing_ratio;  /* min/max |pivot| below this => singular */
     double tol_predict; /* a predicted point whose first correction exceeds this is rejected */
     int max_polish, max_newton, max_end, max_steps, max_iters;
-    int predictor;      /* 0: Euler; 1: cubic Hermite through the last two accepted points */
+    int predictor;      /* 0: Euler; 1: cubic Hermite through the last two accepted points;
+                           2: classical Runge-Kutta (three more evaluations per step) */
 } or_params;
 
 /* Cubic Hermite predictor (the predictor family of Sec. 2.3 built on the Euler direction): the
@@ -401,6 +402,53 @@ static void hermite(int n, double s0, const cplx *z0, const cplx *e0, double s1,
         out[j] = h00 * z0[j] + h10 * d * e0[j] + h01 * z1[j] + h11 * d * e1[j];
 }
 
+/* Classical fourth-order Runge-Kutta predictor (Sec. 2.3's Runge-Kutta family, built on the Euler
+ * direction: dz/ds = dE(z, s)).  From the accepted point (z_a, s_a) with k1 = dE(z_a, s_a):
+ *   k2 = dE(z_a + h/2 k1, s_a + h/2),  k3 = dE(z_a + h/2 k2, s_a + h/2),
+ *   k4 = dE(z_a + h k3, s_a + h),       z = z_a + h/6 (k1 + 2 k2 + 2 k3 + k4).
+ * Stage j = 1, 2, 3 evaluates at rk_stage_point(j); rk_accumulate adds its direction with the
+ * weight of k_{j+1}. */
+static double rk_stage_offset(int j, double h) { return j < 3 ? 0.5 * h : h; }
+static void rk_stage_point(int n, int j, double h, const cplx *za, const cplx *k, cplx *z) {
+    const double a = rk_stage_offset(j, h);
+    for (int i = 0; i < n; i++) z[i] = za[i] + a * k[i];
+}
+static void rk_accumulate(int n, int j, const cplx *k, cplx *ksum) {
+    const double wgt = j < 3 ? 2.0 : 1.0;
+    for (int i = 0; i < n; i++) ksum[i] += wgt * k[i];
+}
+static void rk_finish(int n, double h, const cplx *za, const cplx *ksum, cplx *z) {
+    for (int i = 0; i < n; i++) z[i] = za[i] + (h / 6.0) * ksum[i];
+}
+
+/* The Runge-Kutta predictor alone, for its tests: from (za[p], sa[p]) with step h[p], through the
+ * same stage functions as the tracker.  Returns -1 for bad n; out[p] = NaN where a stage
+ * evaluation is singular. */
+int oracle_rk4_predict(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                       int64_t P, const double *za, const double *sa, const double *h,
+                       double *out) {
+    if (n < 1 || n > OR_NMAX) return -1;
+    for (int64_t p = 0; p < P; p++) {
+        const cplx *z0 = (const cplx *)za + p * n;
+        cplx *zo = (cplx *)out + p * n;
+        cplx dE[OR_NMAX], dN[OR_NMAX], ksum[OR_NMAX], zs[OR_NMAX];
+        double ratio;
+        int bad = step_point(n, m, A, w, (const cplx *)c, z0, sa[p], dE, dN, &ratio, NULL);
+        for (int i = 0; i < n; i++) ksum[i] = dE[i];
+        for (int j = 1; j <= 3 && !bad; j++) {
+            rk_stage_point(n, j, h[p], z0, dE, zs);
+            bad = step_point(n, m, A, w, (const cplx *)c, zs, sa[p] + rk_stage_offset(j, h[p]), dE,
+                             dN, &ratio, NULL);
+            rk_accumulate(n, j, dE, ksum);
+        }
+        if (bad)
+            for (int i = 0; i < n; i++) zo[i] = NAN;
+        else
+            rk_finish(n, h[p], z0, ksum, zo);
+    }
+    return 0;
+}
+
 /* The predictor alone, for its tests: P independent evaluations (complex arrays [P][n]). */
 int oracle_hermite(int n, int64_t P, const double *s0, const double *z0, const double *e0,
                    const double *s1, const double *z1, const double *e1, const double *s,
@@ -415,7 +463,7 @@ int oracle_hermite(int n, int64_t P, const double *s0, const double *z0, const d
 enum { OR_OK = 0, OR_START = 1, OR_RUNNING = 2, OR_SINGULAR = -1, OR_STEP_MIN = -2,
        OR_DIVERGED = -3, OR_NONFINITE = -4, OR_POLISH_FAIL = -5, OR_ENDGAME_FAIL = -6,
        OR_MAX_ITERS = -7 };
-enum { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
+enum { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3, PH_RK = 4 };
 
 static double norm_inf(int n, const cplx *v) {
     double r = 0.0;
@@ -434,7 +482,9 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
     if (*status != OR_START && *status != OR_RUNNING) return;
     cplx za[OR_NMAX], dEa[OR_NMAX], dE[OR_NMAX], dN[OR_NMAX];
     cplx zp[OR_NMAX], dEp[OR_NMAX]; /* the accepted point before (z_a, s_a), for the Hermite predictor */
-    double s = *s_io, sa = s, ds = *ds_io, nrm_prev = 0.0, sp = 0.0;
+    cplx ksum[OR_NMAX];              /* the Runge-Kutta predictor's weighted sum of directions */
+    double s = *s_io, sa = s, ds = *ds_io, nrm_prev = 0.0, sp = 0.0, h_rk = 0.0, st_rk = 0.0;
+    int rk = 0;                      /* the Runge-Kutta stage being evaluated (PH_RK) */
     int have_a = 0, have_p = 0;     /* accepted points held in (za, sa) and (zp, sp) */
     int phase = (*status == OR_START) ? PH_POLISH : PH_RESUME;
     if (*status == OR_START) ds = pr->ds0;
@@ -447,14 +497,29 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
         cnt[3]++;
         double nrm = norm_inf(n, dN);
         if (sing || ratio < pr->sing_ratio) {
-            if (phase == PH_TRACK) goto reject; /* step back and shrink */
+            if (phase == PH_TRACK || phase == PH_RK) goto reject; /* step back and shrink */
             *status = OR_SINGULAR;
             break;
         }
         if (!isfinite(nrm) || !isfinite(norm_inf(n, dE))) {
-            if (phase == PH_TRACK) goto reject;
+            if (phase == PH_TRACK || phase == PH_RK) goto reject;
             *status = OR_NONFINITE;
             break;
+        }
+        if (phase == PH_RK) {
+            /* a Runge-Kutta stage point: its Euler direction is k_{rk+1} */
+            rk_accumulate(n, rk, dE, ksum);
+            if (rk < 3) {
+                rk_stage_point(n, rk + 1, h_rk, za, dE, z);
+                s = (rk + 1 < 3) ? sa + 0.5 * h_rk : st_rk;
+                rk++;
+            } else {
+                rk_finish(n, h_rk, za, ksum, z);
+                s = st_rk;
+                k = 0;
+                phase = PH_TRACK;
+            }
+            continue;
         }
         if (phase == PH_POLISH) {
             for (int j = 0; j < n; j++) z[j] += dN[j];
@@ -521,6 +586,16 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
     predict: {
         double h = fmin(ds, -sa);
         const double st = (h == -sa) ? 0.0 : sa + h;
+        if (pr->predictor == 2) { /* Runge-Kutta: three stage evaluations first */
+            for (int j = 0; j < n; j++) ksum[j] = dEa[j];
+            h_rk = h;
+            st_rk = st;
+            rk = 1;
+            rk_stage_point(n, 1, h, za, dEa, z);
+            s = sa + 0.5 * h;
+            phase = PH_RK;
+            continue;
+        }
         if (pr->predictor == 1 && have_p && h <= 4.0 * (sa - sp))
             hermite(n, sp, zp, dEp, sa, za, dEa, st, z);  /* cubic through the last two points */
         else
@@ -549,7 +624,7 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
 
 /* Track P paths.  dparams: ds0, ds_max, ds_min, tol_polish, tol_track, tol_end, res_tol, div_re,
  * sing_ratio, tol_predict; iparams: max_polish, max_newton, max_end, max_steps, max_iters,
- * predictor (0 Euler, 1 cubic Hermite). */
+ * predictor (0 Euler, 1 cubic Hermite, 2 Runge-Kutta). */
 int oracle_track(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
                  int64_t P, double *z, double *s, double *ds, const double *dparams,
                  const int32_t *iparams, int32_t *status, int32_t *counters, int threads) {

@@ -22,6 +22,9 @@ int oracle_residual(int n, const int32_t *m, const int8_t *A, const double *c, i
 int oracle_endpoint_grad(int n, const int32_t *m, const int8_t *A, const double *w,
                          const double *c, int64_t P, const double *z_end, const double *grad_x,
                          double *grad_c);
+int oracle_rk4_predict(int n, const int32_t *m, const int8_t *A, const double *w, const double *c,
+                       int64_t P, const double *za, const double *sa, const double *h,
+                       double *out);
 
 static uint64_t rng_state = 88172645463325252ull;
 static double urand(void) { /* xorshift64, uniform in [0, 1) */
@@ -74,7 +77,12 @@ static int run(int n, int mk, int P, int threads, int track) {
         const int32_t ip[6] = {10, 3, 8, 50, 200, 1};
         for (int p = 0; p < P; p++) st[p] = 1;
         bad |= oracle_track(n, m, A, w, c, P, z, s, ds, dp, ip, st, cnt, threads) != 0;
+        const int32_t ip_rk[6] = {10, 3, 8, 50, 200, 2}; /* the Runge-Kutta predictor */
+        for (int p = 0; p < P; p++) { st[p] = 1; s[p] = -8.0 * urand(); }
+        bad |= oracle_track(n, m, A, w, c, P, z, s, ds, dp, ip_rk, st, cnt, threads) != 0;
     }
+    for (int p = 0; p < P; p++) ds[p] = 0.1; /* the steps of the predictor alone */
+    bad |= oracle_rk4_predict(n, m, A, w, c, P, z, s, ds, dE) != 0;
     /* out-of-range n is rejected before any array is touched */
     bad |= oracle_eval(n + 40, m, A, w, c, P, z, s, 1, G, L, den, threads) != -1;
     bad |= oracle_residual(0, m, A, c, P, z, res, threads) != -1;

@@ -222,3 +222,81 @@ def test_hermite_tracker_same_roots():
     dim = np.abs(np.angle(np.exp(1j * (a[0].imag - b[0].imag)))).max(1)
     assert np.maximum(dre, dim).max() <= 1e-12
     assert b[4][:, 3].sum() < a[4][:, 3].sum() and ev[1] < ev[0]
+
+
+# ---- the Runge-Kutta predictor (Sec. 2.3: Runge-Kutta methods on the Euler direction) ---------
+def _trinomial():
+    """n = 1: c0 + c1 x t^{w1} + c2 x^2 t^{w2}; its paths have the closed form of the quadratic
+    formula, z(s) = log x(s)."""
+    c = np.array([1.0 + 0.0j, -3.0 + 0.5j, 2.0 - 0.25j])
+    w = np.array([0.0, 1.0, 3.0])
+    sys_ = W.System(1, np.array([3], np.int32), np.array([[0], [1], [2]], np.int8), w, c)
+
+    def z_exact(s, near):
+        t = np.exp(s)
+        a, b, cc = c[2] * t ** w[2], c[1] * t ** w[1], c[0] * t ** w[0]
+        d = np.sqrt(b * b - 4 * a * cc + 0j)
+        roots = np.log(np.array([(-b + d) / (2 * a), (-b - d) / (2 * a)]))
+        roots = roots.real + 1j * (near.imag + np.angle(np.exp(1j * (roots.imag - near.imag))))
+        return roots[np.argmin(np.abs(roots - near))]
+    return sys_, z_exact
+
+
+def _order(err):
+    return np.log2(err[:-1] / err[1:])
+
+
+def test_rk4_predictor_fourth_order():
+    """The predictor's error against the closed-form path shrinks like h^5 (local error of a
+    fourth-order method): halving h divides it by about 32; a plausible mistake in the weights
+    (equal weights) or the stage points (all at s_a + h/2) loses that order."""
+    sys_, z_exact = _trinomial()
+    sa = -1.0
+    z0 = np.array([z_exact(sa, 0.0 + 0.0j)])  # the path through the root nearest z = 0
+    hs = np.array([0.2, 0.1, 0.05, 0.025])
+    got = np.array([oracle.rk4_predict(sys_, sys_.c, z0[None, :], sa, h)[0, 0] for h in hs])
+    ref = np.array([z_exact(sa + h, z0[0]) for h in hs])
+    err = np.abs(got - ref)
+    order = _order(err)
+    assert (order > 4.5).all() and (order < 5.6).all(), order
+
+    def de(z, s):
+        return oracle.step(sys_, sys_.c, np.array([[z]]), np.array([s]))[0][0, 0]
+
+    def bad_rk(h, weights=(1, 2, 2, 1), mid=(0.5, 0.5, 1.0)):
+        z = z0[0]
+        k1 = de(z, sa)
+        k2 = de(z + mid[0] * h * k1, sa + mid[0] * h)
+        k3 = de(z + mid[1] * h * k2, sa + mid[1] * h)
+        k4 = de(z + mid[2] * h * k3, sa + mid[2] * h)
+        return z + h / sum(weights) * (weights[0] * k1 + weights[1] * k2 + weights[2] * k3 + weights[3] * k4)
+    good = np.abs(np.array([bad_rk(h) for h in hs]) - ref)
+    np.testing.assert_allclose(good, err, rtol=1e-6, atol=1e-15)  # the same scheme, by hand
+    for kw in ({"weights": (1, 1, 1, 1)}, {"mid": (0.5, 0.5, 0.5)}):
+        e = np.abs(np.array([bad_rk(h, **kw) for h in hs]) - ref)
+        assert _order(e).min() < 4.0
+
+
+def test_rk4_tracker_same_roots_fewer_steps():
+    """Tracking with the Runge-Kutta predictor ends every path on the Euler predictor's endpoint
+    (path by path: the c1 cells and 300 n = 8 planted-cell paths), in fewer accepted steps."""
+    base, cells = W.c1_cells()
+    steps = {0: 0, 2: 0}
+    for csys, info, z0 in cells:
+        res = {}
+        for pred in (0, 2):
+            ze, _, _, st, cnt = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=pred))
+            assert (st == oracle.OK).all()
+            res[pred] = ze
+            steps[pred] += int(cnt[:, 0].sum())
+        dre = np.abs(res[0].real - res[2].real)
+        dim = np.abs(np.angle(np.exp(1j * (res[0].imag - res[2].imag))))
+        assert np.maximum(dre, dim).max() <= 1e-12
+    csys, cell, z0 = W.planted_config("c5", P=300)
+    a = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=0))
+    b = oracle.track(csys, csys.c, z0, -32.0, oracle.TrackParams(predictor=2))
+    assert (a[3] == 0).all() and (b[3] == 0).all()
+    dre = np.abs(a[0].real - b[0].real).max(1)
+    dim = np.abs(np.angle(np.exp(1j * (a[0].imag - b[0].imag)))).max(1)
+    assert np.maximum(dre, dim).max() <= 1e-12
+    assert b[4][:, 0].sum() < a[4][:, 0].sum() and steps[2] < steps[0]
