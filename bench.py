@@ -735,7 +735,8 @@ def main():
     legs = (("fp64", hom.FP64, {}), ("mixed", hom.MIXED, {}),
             ("fp64_tol_track_1e-5", hom.FP64, {"tol_track": 1e-5}),
             ("mixed_hermite", hom.MIXED, {"predictor": hom.PREDICT_HERMITE}),
-            ("fp64_hermite", hom.FP64, {"predictor": hom.PREDICT_HERMITE}))
+            ("fp64_hermite", hom.FP64, {"predictor": hom.PREDICT_HERMITE}),
+            ("mixed_rk4", hom.MIXED, {"predictor": hom.PREDICT_RK4}))
     for name, prec, kw in legs:
         res[name] = run_form(hom, torch, h, csys, z0, prec, args.steps, args.warmup, **kw)
         print(f"# {name}: {res[name]['rate']:.4e} {UNIT}, {res[name]['ms_per_step']:.2f} ms/step, "
@@ -776,7 +777,9 @@ def main():
         "fp64_tol_track_1e-5": form_rec(res["fp64_tol_track_1e-5"]),
         "mixed_hermite": form_rec(res["mixed_hermite"]),
         "fp64_hermite": form_rec(res["fp64_hermite"]),
+        "mixed_rk4": form_rec(res["mixed_rk4"]),
         "endpoints_mixed_hermite_vs_fp64": compare_endpoints(res["mixed_hermite"], res["fp64"]),
+        "endpoints_mixed_rk4_vs_fp64": compare_endpoints(res["mixed_rk4"], res["fp64"]),
         "endpoints_mixed_vs_fp64": compare_endpoints(mixed, res["fp64"]),
         "endpoints_fp64_tol_track_1e-5_vs_fp64": compare_endpoints(res["fp64_tol_track_1e-5"],
                                                                    res["fp64"]),
@@ -784,6 +787,7 @@ def main():
     }
     out["mixed"].pop("roofline_frac_fp64_peak")
     out["mixed_hermite"].pop("roofline_frac_fp64_peak")
+    out["mixed_rk4"].pop("roofline_frac_fp64_peak")
     if not args.no_dense:
         out["eval_step_n10_65536_points"] = run_eval_n10(hom, torch, P=65536)
         out["eval_step_n10_1M_points"] = run_eval_n10(hom, torch, P=1 << 20)

@@ -197,7 +197,7 @@ typedef struct {
                            HOM_TRACK_SIDE_NOWAIT */
     int32_t tile;       /* batched form: paths per work item = tile x lane groups per block
                            (0: the default, 4) */
-    int32_t predictor;  /* HOM_PREDICT_EULER (default) or HOM_PREDICT_HERMITE */
+    int32_t predictor;  /* HOM_PREDICT_EULER (default), HOM_PREDICT_HERMITE or HOM_PREDICT_RK4 */
 } hom_track_params;
 
 /* hom_track_params.predictor.  Euler: z = z_a + h dz_euler(z_a) (Sec. 2.3).  Hermite: the cubic
@@ -208,6 +208,14 @@ typedef struct {
  * bitwise the uninterrupted one with this predictor, though it reaches the same endpoints). */
 #define HOM_PREDICT_EULER 0
 #define HOM_PREDICT_HERMITE 1
+/* Runge-Kutta (Sec. 2.3 names Runge-Kutta predictors built on the Euler direction): the
+ * classical fourth-order scheme on dz/ds = dE(z, s) from the accepted point,
+ *   k2 = dE(z_a + h/2 k1, s_a + h/2), k3 = dE(z_a + h/2 k2, s_a + h/2), k4 = dE(z_a + h k3, s_a + h),
+ *   z = z_a + h/6 (k1 + 2 k2 + 2 k3 + k4);
+ * three more eval+solves per step (counted like the others); a stage point whose evaluation
+ * fails, or whose Newton step exceeds tol_predict (outside the corrector's trust region, as for
+ * the predicted point), rejects the step. */
+#define HOM_PREDICT_RK4 2
 
 /* hom_track_params.flags: recompute every row's maximum (the e^{-M_k} row shift) at every
  * evaluation instead of reusing the previous evaluation's maximum.  Slower (one more pass over

@@ -507,7 +507,11 @@ static void track_path(int n, const int32_t *m, const int8_t *A, const double *w
             break;
         }
         if (phase == PH_RK) {
-            /* a Runge-Kutta stage point: its Euler direction is k_{rk+1} */
+            /* a Runge-Kutta stage point: its Euler direction is k_{rk+1}.  Like the predicted
+             * point, every stage point must lie in the corrector's trust region (its Newton step
+             * at most tol_predict); otherwise the stages have left the path's neighbourhood and
+             * the step is rejected */
+            if (nrm > pr->tol_predict) goto reject;
             rk_accumulate(n, rk, dE, ksum);
             if (rk < 3) {
                 rk_stage_point(n, rk + 1, h_rk, za, dE, z);

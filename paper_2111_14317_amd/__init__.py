@@ -31,7 +31,7 @@ PATH_OK, PATH_START, PATH_RUNNING = 0, 1, 2
 PATH_SINGULAR, PATH_STEP_MIN, PATH_DIVERGED, PATH_NONFINITE = -1, -2, -3, -4
 PATH_POLISH_FAIL, PATH_ENDGAME_FAIL, PATH_MAX_ITERS = -5, -6, -7
 TRACK_EXACT_SHIFT, TRACK_SERIAL, TRACK_SIDE_NOWAIT = 1, 2, 4
-PREDICT_EULER, PREDICT_HERMITE = 0, 1
+PREDICT_EULER, PREDICT_HERMITE, PREDICT_RK4 = 0, 1, 2
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_step_proj", "hom_track_params_default", "hom_track", "hom_track_noalloc",

@@ -735,7 +735,8 @@ static int check_track_args(const char *fn, hom_system_t h, const double *c, int
       params->max_steps < 0 || params->max_iters < 1 ||
       (params->flags & ~(HOM_TRACK_EXACT_SHIFT | HOM_TRACK_SERIAL | HOM_TRACK_SIDE_NOWAIT)) ||
       params->tile < 0 ||
-      (params->predictor != HOM_PREDICT_EULER && params->predictor != HOM_PREDICT_HERMITE))
+      (params->predictor != HOM_PREDICT_EULER && params->predictor != HOM_PREDICT_HERMITE &&
+       params->predictor != HOM_PREDICT_RK4))
     HOM_FAIL(HOM_EINVAL, f + ": bad params");
   if (P == 0) {
     *nothing_to_do = true;

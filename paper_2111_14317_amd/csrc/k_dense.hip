@@ -122,7 +122,7 @@ __device__ __forceinline__ float row_max(const DenseDev &D, int t0, int t1, int 
                                          const bf16x8_t zh, float sf) {
   float m = -INFINITY;
   const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll 1  // (a loop holding an MFMA is not unrolled with a remainder)
   for (int t = t0; t < t1; ++t) {
     const f32x4_t d = mfma_bf16(as_bf16x8(D.EAb[t * 64 + lane]), zh, zero);
 #pragma unroll
@@ -189,11 +189,11 @@ __device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restri
 // like store_row, with the column scale e^{M} formed once per lane and passed by shuffle, and
 // the e^{-z_j} factors of HOM_AFFINE formed one (row, column tile) at a time with the polynomial
 // exp and sin/cos, so that the store stays small next to the contraction's registers.
-template <typename OutT, int NCT, class Coef>
+template <typename OutT, int NCT, class Coef, typename AccT = f64x4_t, bool F64 = true>
 __device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__restrict__ logscale,
                                                int flags, int64_t p0, int64_t pb, int64_t p1,
                                                int n, int k, int q, int c16,
-                                               const f64x4_t (&aR)[2], const f64x4_t (&aI)[2],
+                                               const AccT (&aR)[2], const AccT (&aI)[2],
                                                Cx<double> H, Cx<double> Hs, double m, double sp,
                                                const double *__restrict__ z, Coef kc) {
   const int ld = n + 2;
@@ -201,16 +201,16 @@ __device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__r
 #pragma unroll 1
   for (int rc = 0; rc < 4 * NCT; ++rc) {
     const int r = rc / NCT, ct = rc % NCT;
-    const int pr = row_f64(q, r);
+    const int pr = F64 ? row_f64(q, r) : row_f32(q, r);
     const int64_t p = pb + pr;
     const double scale = __shfl(own, pr);
     const int col = 16 * ct + c16;
-    double vr = aR[0][0], vi = aI[0][0];
+    double vr = (double)aR[0][0], vi = (double)aI[0][0];
 #pragma unroll
     for (int u = 0; u < 4 * NCT; ++u)
       if (u == rc) {
-        vr = aR[u % NCT][u / NCT];
-        vi = aI[u % NCT][u / NCT];
+        vr = (double)aR[u % NCT][u / NCT];
+        vi = (double)aI[u % NCT][u / NCT];
       }
     if (p < p1 && col < n) {
       Cx<double> v = {vr * scale, vi * scale};
@@ -247,13 +247,23 @@ __device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__r
 // LW: the liftings and the FP32 coefficients (16 bytes per monomial) are staged in LDS once per
 // block, when they fit kDenseLdsBytes; else read from global memory per term.
 constexpr size_t kDenseLdsBytes = 64 * 1024;
+constexpr size_t kCuLdsBytes = 160 * 1024;  // LDS of one CU
 
-template <typename OutT, bool LW>
-__global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2)))
+#ifndef HOM_BF16_WAVES
+#define HOM_BF16_WAVES 4  // waves per block (they share the block's staged tables)
+#endif
+#ifndef HOM_BF16_EU
+#define HOM_BF16_EU 2  // waves per SIMD the register budget is set for
+#endif
+constexpr int kBf16Block = 64 * HOM_BF16_WAVES;
+template <typename OutT, bool LW, int NCT>
+__global__ void __launch_bounds__(kBf16Block) __attribute__((amdgpu_waves_per_eu(HOM_BF16_EU)))
     k_dense_bf16(DenseDev D, const Cx<float> *__restrict__ Cf, int64_t p0, int64_t p1,
                  const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
                  double *__restrict__ logscale, int flags, unsigned long long *units) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ double sK[kCoefCount];  // the polynomial constants of exp and sin/cos (the store)
+  stage_coefficients(sK);
   const double *Wt = D.W;
   const Cx<float> *Ct = Cf;
   if constexpr (LW) {
@@ -263,16 +273,16 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       sW[i] = D.W[i];
       sC[i] = Cf[i];
     }
-    __syncthreads();
     Wt = sW;
     Ct = sC;
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
-  const int n = D.n, nct = D.nct;
+  const int n = D.n;  // NCT = D.nct
   const int64_t ntile = (p1 - p0 + 15) >> 4;
   const f32x4_t zero = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile;
-       tile += (int64_t)gridDim.x * 4) {
+  for (int64_t tile = (int64_t)blockIdx.x * HOM_BF16_WAVES + (threadIdx.x >> 6); tile < ntile;
+       tile += (int64_t)gridDim.x * HOM_BF16_WAVES) {
     const int64_t pb = p0 + tile * 16, pl = pb + c16;
     const bool lv = pl < p1;
     // B operands: lane (c16, q) holds coordinates 8q .. 8q+7 of point c16
@@ -315,7 +325,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         eaN[u] = D.EAb[(2 * ch0 + u) * 64 + lane];
-        cbN[u] = u < nct ? D.CBb[(ch0 * 2 + u) * 64 + lane] : uint4{0, 0, 0, 0};
+        cbN[u] = u < NCT ? D.CBb[(ch0 * 2 + u) * 64 + lane] : uint4{0, 0, 0, 0};
       }
 #pragma unroll 1
       for (int ch = ch0; ch < ch1; ++ch) {
@@ -325,7 +335,7 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             eaN[u] = D.EAb[(2 * (ch + 1) + u) * 64 + lane];
-            if (u < nct) cbN[u] = D.CBb[((ch + 1) * 2 + u) * 64 + lane];
+            if (u < NCT) cbN[u] = D.CBb[((ch + 1) * 2 + u) * 64 + lane];
           }
         }
 #pragma unroll
@@ -378,16 +388,14 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
         const bf16x8_t r0 = pack8(vr[0]), r1 = pack8(vr[1]), r2 = pack8(vr[2]);
         const bf16x8_t i0 = pack8(vi[0]), i1 = pack8(vi[1]), i2 = pack8(vi[2]);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          if (ct < nct) {
-            const bf16x8_t cb = as_bf16x8(cbC[ct]);
-            aR[ct] = mfma_bf16(r2, cb, aR[ct]);
-            aR[ct] = mfma_bf16(r1, cb, aR[ct]);
-            aR[ct] = mfma_bf16(r0, cb, aR[ct]);
-            aI[ct] = mfma_bf16(i2, cb, aI[ct]);
-            aI[ct] = mfma_bf16(i1, cb, aI[ct]);
-            aI[ct] = mfma_bf16(i0, cb, aI[ct]);
-          }
+        for (int ct = 0; ct < NCT; ++ct) {
+          const bf16x8_t cb = as_bf16x8(cbC[ct]);
+          aR[ct] = mfma_bf16(r2, cb, aR[ct]);
+          aR[ct] = mfma_bf16(r1, cb, aR[ct]);
+          aR[ct] = mfma_bf16(r0, cb, aR[ct]);
+          aI[ct] = mfma_bf16(i2, cb, aI[ct]);
+          aI[ct] = mfma_bf16(i1, cb, aI[ct]);
+          aI[ct] = mfma_bf16(i0, cb, aI[ct]);
         }
       }
       hr += __shfl_xor(hr, 16);
@@ -398,8 +406,9 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
       sr += __shfl_xor(sr, 32);
       si += __shfl_xor(si, 16);
       si += __shfl_xor(si, 32);
-      store_row<OutT, f32x4_t, false>(G, logscale, flags, p0, pb, p1, n, nct, k, q, c16, aR, aI,
-                               Cx<double>{hr, hi}, Cx<double>{sr, si}, Mk, sp, z);
+      store_row_lean<OutT, NCT, CoefLds, f32x4_t, false>(
+          G, logscale, flags, p0, pb, p1, n, k, q, c16, aR, aI, Cx<double>{hr, hi},
+          Cx<double>{sr, si}, Mk, sp, z, CoefLds{sK, PointLds{}.fresh()});
     }
     if (units && lane == 0) {
       const int64_t cnt = p1 - pb < 16 ? p1 - pb : 16;
@@ -570,7 +579,6 @@ __global__ void __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_e
 // ------------------------------------------------------------------------------------------
 constexpr int kUnionWaves = 4;
 constexpr int kUnionBlock = 64 * kUnionWaves;
-constexpr size_t kCuLdsBytes = 160 * 1024;  // LDS of one CU
 constexpr size_t kUnionCoefBytes = (kCoefCount * 8 + 15) / 16 * 16;
 #ifndef HOM_UNION_WAVES
 #define HOM_UNION_WAVES 3
@@ -847,14 +855,29 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
   unsigned long long *units = prof_units(stream);
   const dim3 grid(dense_grid(p1 - p0)), block(kDenseBlock);
   const size_t lw = (size_t)S.Md * 16;
-  if (engine == 1 && lw <= kDenseLdsBytes) {  // two blocks per CU hold the staged tables
-    const int64_t cap = 2 * (int64_t)num_cus();
-    const dim3 g2((unsigned)(grid.x < cap ? grid.x : cap));
-    hipLaunchKernelGGL((k_dense_bf16<OutT, true>), g2, block, lw, stream, S.dense, Cf, p0, p1, z,
-                       s, G, logscale, flags, units);
-  } else if (engine == 1) {
-    hipLaunchKernelGGL((k_dense_bf16<OutT, false>), grid, block, 0, stream, S.dense, Cf, p0, p1, z,
-                       s, G, logscale, flags, units);
+  if (engine == 1) {
+    const int64_t tiles = (p1 - p0 + 15) / 16, need = (tiles + HOM_BF16_WAVES - 1) / HOM_BF16_WAVES;
+    const dim3 bb(kBf16Block);
+    if (lw <= kDenseLdsBytes) {  // the blocks that fit a CU's LDS hold the staged tables
+      const int64_t per = (int64_t)(kCuLdsBytes / lw) < 8 ? (int64_t)(kCuLdsBytes / lw) : 8;
+      const int64_t cap = per * (int64_t)num_cus();
+      const dim3 g2((unsigned)(need < cap ? (need > 0 ? need : 1) : cap));
+      if (S.dense.nct == 1)
+        hipLaunchKernelGGL((k_dense_bf16<OutT, true, 1>), g2, bb, lw, stream, S.dense, Cf, p0, p1,
+                           z, s, G, logscale, flags, units);
+      else
+        hipLaunchKernelGGL((k_dense_bf16<OutT, true, 2>), g2, bb, lw, stream, S.dense, Cf, p0, p1,
+                           z, s, G, logscale, flags, units);
+    } else {
+      const int64_t cap = (int64_t)num_cus() * 8;
+      const dim3 g1((unsigned)(need < cap ? (need > 0 ? need : 1) : cap));
+      if (S.dense.nct == 1)
+        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 1>), g1, bb, 0, stream, S.dense, Cf, p0, p1,
+                           z, s, G, logscale, flags, units);
+      else
+        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 2>), g1, bb, 0, stream, S.dense, Cf, p0, p1,
+                           z, s, G, logscale, flags, units);
+    }
   } else if (S.union_support) {  // common support: the exponentials once per point
     const size_t lds = kUnionCoefBytes + (size_t)S.union_tiles * 4 * 64 * 16;
     const int64_t tiles = (p1 - p0 + 15) / 16;

@@ -19,6 +19,9 @@
 //   predict  : z = z_a + h dE_a, s = s_a + h, h = min(ds, -s_a) (Euler); or, with the Hermite
 //              predictor, the cubic through the last two accepted points and their Euler
 //              directions (when h <= 4 (s_a - s_p); the first step after a claim is Euler);
+//              or the classical Runge-Kutta scheme on dz/ds = dE, its three stage points
+//              evaluated one per iteration (phases PH_RK1..PH_RK3; a failed stage rejects the
+//              step);
 //   endgame  : at s = 0 Newton until ||dN|| <= tol_end (1 + ||z||), max_end iterations, or the
 //              step stops contracting; OK when the relative residual <= res_tol.
 // The CPU oracle runs the same rules with the same constants.
@@ -46,7 +49,8 @@ namespace hom {
 
 constexpr int kTrackBlock = 256;
 
-enum : int { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3 };
+// PH_RK1..PH_RK3: evaluating the Runge-Kutta predictor's stage point 1..3
+enum : int { PH_POLISH = 0, PH_TRACK = 1, PH_END = 2, PH_RESUME = 3, PH_RK1 = 4, PH_RK3 = 6 };
 enum : int { ACT_NONE = 0, ACT_REJECT = 1, ACT_PREDICT = 2, ACT_END = 3 };
 
 // mixed form: a path with this many consecutive rejected steps is handed to FP64.  Near an
@@ -86,7 +90,9 @@ __device__ __forceinline__ void load_point_lds(const Cx<double> *sZc, int n, dou
 // Groups claim paths through `queue` (global memory for a whole launch, or LDS for one work item of
 // the batched form).  Path p's point is z[p * zstride + j], j < n.  slot_state: LDS for the
 // block's groups (track_state_bytes).
-template <int N, bool MIXED>
+// RK: the Runge-Kutta predictor's phases are compiled in (the FP32 launch has a variant without
+// them, launched unless that predictor is asked for).
+template <int N, bool MIXED, bool RK = true>
 __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double> *slot_state,
                                             int64_t p_begin, int64_t p_end, int zstride,
                                             double *__restrict__ z, double *__restrict__ s,
@@ -112,6 +118,9 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
   Cx<double> *sZc = sZa + 4 * N;
   Cx<double> *sZp = sZa + 5 * N;  // the accepted point before (z_a, s_a), and its Euler direction
   Cx<double> *sEp = sZa + 6 * N;  // (the Hermite predictor's second point)
+  // the Runge-Kutta predictor's sum k1 + 2 k2 + 2 k3 + k4, in the Hermite predictor's slot (the
+  // two are never used together; an acceptance overwrites it only after the stages are done)
+  Cx<double> *sKs = sZp;
   const int64_t P = p_end - p_begin;
 
   double zo_r = 0.0, zo_i = 0.0;  // this lane's own coordinate z_r of the current point
@@ -315,7 +324,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     // ---- scalar update of the slot (divergent across groups, identical within a group) ----
     bool fin = false, park = false;
     int fst = 0;
-    if (MIXED && iters >= pr.max_iters / 8 && phase == PH_TRACK) {
+    if (MIXED && iters >= pr.max_iters / 8 && (phase == PH_TRACK || (RK && phase >= PH_RK1))) {
       park = true;  // an eighth of the iteration budget spent in FP32: FP64 takes over
       fst = kParked;
       ds = pr.ds0;
@@ -333,16 +342,46 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
       const bool bad_lu = sing || !(ratio >= sing_ratio);
       const bool nonfin = !(nN <= INFINITY) || !(nE <= INFINITY);
       int act = ACT_NONE;
-      if (MIXED && (bad_lu || nonfin) && phase != PH_TRACK) {
+      if (MIXED && (bad_lu || nonfin) && phase != PH_TRACK && !(RK && phase >= PH_RK1)) {
         park = true;  // the accepted point itself: re-tracked in FP64 from there
         fst = kParked;
         ds = pr.ds0;
-      } else if (bad_lu || nonfin) {  // a predicted or corrected point: a rejected step
-        if (phase == PH_TRACK) {
+      } else if (bad_lu || nonfin) {  // a predicted, stage or corrected point: a rejected step
+        if (phase == PH_TRACK || (RK && phase >= PH_RK1)) {
           act = ACT_REJECT;
         } else {
           fin = true;
           fst = bad_lu ? -1 : -4;
+        }
+      } else if (RK && phase >= PH_RK1 && nrm > pr.tol_predict) {
+        act = ACT_REJECT;  // a stage point outside the corrector's trust region
+      } else if (RK && phase >= PH_RK1) {
+        // a Runge-Kutta stage point: its Euler direction is k_{j+1}, j = the stage (each lane
+        // its own coordinate); the step h and its end are those of the prediction (ds and s_a
+        // do not change during the stages)
+        const int j = phase - PH_RK1 + 1;
+        const double hstep = fmin(ds, -sa), st = (hstep == -sa) ? 0.0 : sa + hstep;
+        if (geo.valid) {
+          const Cx<double> za = sZa[r], ks = sKs[r];
+          const double wgt = j < 3 ? 2.0 : 1.0;
+          const Cx<double> kn = {fma(wgt, e.x, ks.x), fma(wgt, e.y, ks.y)};
+          if (j < 3) {  // the next stage point: z_a + h/2 k2, then z_a + h k3
+            const double a = j + 1 < 3 ? 0.5 * hstep : hstep;
+            zo_r = fma(a, e.x, za.x);
+            zo_i = fma(a, e.y, za.y);
+            sKs[r] = kn;
+          } else {  // the predicted point z_a + h/6 (k1 + 2 k2 + 2 k3 + k4)
+            zo_r = fma(hstep / 6.0, kn.x, za.x);
+            zo_i = fma(hstep / 6.0, kn.y, za.y);
+          }
+        }
+        if (j < 3) {
+          sc = j + 1 < 3 ? sa + 0.5 * hstep : st;
+          ++phase;
+        } else {
+          sc = st;
+          k = 0;
+          phase = PH_TRACK;
         }
       } else if (phase == PH_POLISH) {
         zo_r = cre;
@@ -438,7 +477,16 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
         const double hstep = fmin(ds, -sa);
         const double st = (hstep == -sa) ? 0.0 : sa + hstep;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        if (geo.valid) {
+        if (RK && pr.predictor == HOM_PREDICT_RK4) {
+          // Runge-Kutta: first the stage point z_a + h/2 k1 at s_a + h/2 (k1 = the Euler
+          // direction at the accepted point)
+          if (geo.valid) {
+            const Cx<double> za = sZa[r], ea = sEa[r];
+            sKs[r] = ea;
+            zo_r = fma(0.5 * hstep, ea.x, za.x);
+            zo_i = fma(0.5 * hstep, ea.y, za.y);
+          }
+        } else if (geo.valid) {
           const Cx<double> za = sZa[r], ea = sEa[r];
           if (pr.predictor == HOM_PREDICT_HERMITE && have_p && hstep <= 4.0 * (sa - sp)) {
             // the cubic through (sp, z_p) and (sa, z_a) with slopes e_p, e_a (Sec. 2.3's
@@ -454,9 +502,14 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
             zo_i = fma(hstep, ea.y, za.y);
           }
         }
-        sc = st;
+        if (RK && pr.predictor == HOM_PREDICT_RK4) {
+          sc = sa + 0.5 * hstep;
+          phase = PH_RK1;
+        } else {
+          sc = st;
+          phase = PH_TRACK;
+        }
         k = 0;
-        phase = PH_TRACK;
       }
       if (act == ACT_END) {
         {
@@ -477,7 +530,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
     if (geo.valid)  // read by the group's next evaluation (zero for the padding unknowns)
       sZc[r] = r < n ? Cx<double>{zo_r, zo_i} : Cx<double>{0.0, 0.0};
     if (park) {  // the last accepted point (in PH_RESUME the current point is that point)
-      if (phase == PH_TRACK) {
+      if (phase == PH_TRACK || (RK && phase >= PH_RK1)) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (geo.valid) {
           zo_r = sZa[r].x;
@@ -522,7 +575,7 @@ __device__ __forceinline__ void track_slots(const SysLds<N> &S, int n, Cx<double
 
 // Single system: all P paths, one global work queue.  At most 256 registers per lane, so two
 // waves share each SIMD (the FP64 form at n = 10 needs slightly more without the bound).
-template <int N, bool MIXED, bool GT>
+template <int N, bool MIXED, bool GT, bool RK = true>
 __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_eu(2)))
     k_track(SysDev sd, const double *__restrict__ c, int64_t P, double *__restrict__ z,
             double *__restrict__ s, double *__restrict__ ds_io, int32_t *__restrict__ status,
@@ -539,12 +592,12 @@ __global__ void __launch_bounds__(kTrackBlock) __attribute__((amdgpu_waves_per_e
   const SysLds<N> S = stage_tables<N, GT>(smem, sd, c);
   if constexpr (MIXED && !GT) {  // the FP32 evaluation's own tables follow the FP64 ones
     const F32Tables<N> ft = stage_f32_tables<N>(smem + table_bytes, S);
-    track_slots<N, MIXED>(S, sd.n,
+    track_slots<N, MIXED, RK>(S, sd.n,
                           reinterpret_cast<Cx<double> *>(smem + table_bytes +
                                                          lds_f32_bytes<N>(sd.n, sd.mmax)),
                           0, P, sd.n, z, s, ds_io, status, counters, pr, queue, units, kcoef, &ft);
   } else {
-    track_slots<N, MIXED>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n,
+    track_slots<N, MIXED, RK>(S, sd.n, reinterpret_cast<Cx<double> *>(smem + table_bytes), 0, P, sd.n,
                           z, s, ds_io, status, counters, pr, queue, units, kcoef);
   }
 }
@@ -559,7 +612,9 @@ static hipError_t track_n(const System &S, const void *cws, const double *c, int
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
   const size_t f32 = (mixed && !S.global_tables) ? lds_f32_bytes<N>(S.n, S.mmax) : 0;
   const size_t lds = tb + f32 + track_state_bytes<N>();
-  auto kern = mixed ? (S.global_tables ? k_track<N, true, true> : k_track<N, true, false>)
+  const bool rk = pr.predictor == HOM_PREDICT_RK4;  // (FP64 launches always carry it)
+  auto kern = mixed ? (S.global_tables ? (rk ? k_track<N, true, true, true> : k_track<N, true, true, false>)
+                                       : (rk ? k_track<N, true, false, true> : k_track<N, true, false, false>))
                     : (S.global_tables ? k_track<N, false, true> : k_track<N, false, false>);
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTrackBlock, lds);
