@@ -133,62 +133,11 @@ __device__ __forceinline__ float row_max(const DenseDev &D, int t0, int t1, int 
   return m;
 }
 
-// e^{-z_j} of point p (the HOM_AFFINE column factor), or 0 outside the points and columns
-__device__ __forceinline__ Cx<double> affine_factor(const double *__restrict__ z, int64_t p,
-                                                    int64_t p1, int n, int j) {
-  if (p >= p1 || j >= n) return {0.0, 0.0};
-  double sn, cs;
-  sincos(-z[2 * (p * n + j) + 1], &sn, &cs);
-  const double mag = exp(-z[2 * (p * n + j)]);
-  return {mag * cs, mag * sn};
-}
-
-// Store row k of G for the tile.  acc*: J_z entries in the MFMA result layout (point row(q, r),
-// column 16 ct + c16); H, Hs: this lane's point c16; m: the row shift of point c16.
-template <typename OutT, typename AccT, bool F64>
-__device__ __forceinline__ void store_row(OutT *__restrict__ G, double *__restrict__ logscale,
-                                          int flags, int64_t p0, int64_t pb, int64_t p1, int n,
-                                          int nct, int k, int q, int c16, const AccT (&aR)[2],
-                                          const AccT (&aI)[2], Cx<double> H, Cx<double> Hs,
-                                          double m, double sp, const double *__restrict__ z) {
-  const int ld = n + 2;
-  if (nct > 0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pr = F64 ? row_f64(q, r) : row_f32(q, r);
-      const int64_t p = pb + pr;
-      const double mp = __shfl(m, pr);
-      const double scale = (flags & 1) ? exp(mp) : 1.0;
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const int col = 16 * ct + c16;
-        if (ct < nct && p < p1 && col < n) {
-          Cx<double> v = {(double)aR[ct][r] * scale, (double)aI[ct][r] * scale};
-          if (flags & 2) v = cmul(v, affine_factor(z, p, p1, n, col));
-          OutT *g = G + 2 * (((p - p0) * n + k) * ld + col);
-          g[0] = (OutT)v.x;
-          g[1] = (OutT)v.y;
-        }
-      }
-    }
-  }
-  const int64_t p = pb + c16;
-  if (q == 0 && p < p1) {
-    const double scale = (flags & 1) ? exp(m) : 1.0;
-    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // H_t = e^{-s} H_s
-    OutT *g = G + 2 * (((p - p0) * n + k) * ld + n);
-    g[0] = (OutT)(Hs.x * fs);
-    g[1] = (OutT)(Hs.y * fs);
-    g[2] = (OutT)(H.x * scale);
-    g[3] = (OutT)(H.y * scale);
-    if (logscale) logscale[p * n + k] = (flags & 1) ? 0.0 : m;
-  }
-}
-
-// Writes one equation's row block of a 16-point tile (the FP64 engines' accumulator layout):
-// like store_row, with the column scale e^{M} formed once per lane and passed by shuffle, and
-// the e^{-z_j} factors of HOM_AFFINE formed one (row, column tile) at a time with the polynomial
-// exp and sin/cos, so that the store stays small next to the contraction's registers.
+// Writes one equation's row block of a 16-point tile from the MFMA accumulators (row layout of
+// the FP64 or the FP32 result), the H_s and H columns, and the row's logscale: the column scale
+// e^{M} (HOM_UNSCALED) is formed once per lane and passed by shuffle, and the e^{-z_j} factors of
+// HOM_AFFINE one (row, column tile) at a time with the polynomial exp and sin/cos, so that the
+// store stays small next to the contraction's registers.
 template <typename OutT, int NCT, class Coef, typename AccT = f64x4_t, bool F64 = true>
 __device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__restrict__ logscale,
                                                int flags, int64_t p0, int64_t pb, int64_t p1,

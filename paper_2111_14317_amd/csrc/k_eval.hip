@@ -86,8 +86,8 @@ __global__ void __launch_bounds__(kBlock)
     double M;
     T absum;
     eval_row_exact<N, T>(S, r, zr, zi, sp, row, M, absum);
-    const double scale = (flags & 1) ? exp(M) : 1.0;  // HOM_UNSCALED
-    const double fs = (flags & 2) ? scale * exp(-sp) : scale;  // HOM_AFFINE: H_t = e^{-s} H_s
+    const double scale = (flags & 1) ? exp_eval(M) : 1.0;  // HOM_UNSCALED
+    const double fs = (flags & 2) ? scale * exp_eval(-sp) : scale;  // HOM_AFFINE: H_t = e^{-s} H_s
     // rows of this wave's block in chunks through the staging buffer
     const int64_t left = P - base;
     const int groups = left < Geo<N>::G ? (int)left : Geo<N>::G;
@@ -117,9 +117,11 @@ __global__ void __launch_bounds__(kBlock)
           double2 v = src[k];
           if (j < n) {
             const Cx<double> zj = sZ[(rq / n) * N + j];
+            double t = -zj.y * kInv2Pi;  // the phase in turns, reduced to [-1/2, 1/2]
+            t -= rint(t);
             double sn, cs;
-            sincos(-zj.y, &sn, &cs);
-            const double mag = exp(-zj.x);
+            sincos_turns(t, sn, cs);
+            const double mag = exp_eval(-zj.x);
             const Cx<double> w = cmul(Cx<double>{v.x, v.y}, Cx<double>{mag * cs, mag * sn});
             v.x = w.x;
             v.y = w.y;
