@@ -795,6 +795,16 @@ def main():
         out["common_support_n32_m128"] = run_union(hom, torch, args.dense_points)
         out["start_points_n10_cell"] = run_starts(hom, torch)
         out["step_proj_n10_65536_points"] = run_step_proj(hom, torch)
+    # the units' rates measured on this device (the published peaks stay the roofline denominators)
+    peaks = hom.peak_probes()
+    out["measured_peaks"] = peaks
+    if out.get("roofline"):
+        t = (FP64_SHARE / (peaks["fp64_fma_tflops"] * 1e12) +
+             (FLOPS_PER_UNIT - FP64_SHARE) / (peaks["fp32_fma_tflops"] * 1e12))
+        m_peak = FLOPS_PER_UNIT / t / 1e12
+        out["roofline"]["measured_peak"] = m_peak
+        out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / m_peak
+    print(f"# measured peaks: {peaks}", file=sys.stderr, flush=True)
     if not args.no_batch:
         out["batch_c4"] = run_c4(hom, torch)
     c5 = None

@@ -326,6 +326,30 @@ int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *be
                         int64_t z_rows, hom_stream_t stream);
 
 /*
+ * Peak probes: the rate of one unit of the device the calling thread has current, measured by a
+ * bounded kernel (the denominators the kernels' rooflines can be set against, beside the
+ * published peaks).  kind and the unit of *rate:
+ *   HOM_PEAK_HBM_READ, HOM_PEAK_HBM_WRITE   GB/s  (a 4 GiB buffer read / written once per launch)
+ *   HOM_PEAK_FP64_FMA, HOM_PEAK_FP32_FMA    TFLOP/s (vector FMA, 2 flops each)
+ *   HOM_PEAK_FP32_EXP2                      G evaluations/s of the hardware exp2
+ *   HOM_PEAK_MFMA_F64, HOM_PEAK_MFMA_BF16   TFLOP/s (16x16x4 f64, 16x16x32 bf16 with FP32 sums)
+ *   HOM_PEAK_EXP_F64, HOM_PEAK_SINCOS_F64   G evaluations/s of this library's FP64 exponential
+ *                                           and sine/cosine pair of the evaluation's terms
+ * Allocates its own buffers (4 GiB for the HBM probes) and blocks until done; not for use under
+ * stream capture.  Errors: HOM_EINVAL (unknown kind, NULL rate), HOM_ENOMEM, HOM_EDEVICE.
+ */
+#define HOM_PEAK_HBM_READ 0
+#define HOM_PEAK_HBM_WRITE 1
+#define HOM_PEAK_FP64_FMA 2
+#define HOM_PEAK_FP32_FMA 3
+#define HOM_PEAK_FP32_EXP2 4
+#define HOM_PEAK_MFMA_F64 5
+#define HOM_PEAK_MFMA_BF16 6
+#define HOM_PEAK_EXP_F64 7
+#define HOM_PEAK_SINCOS_F64 8
+int hom_peak_probe(int kind, double *rate, hom_stream_t stream);
+
+/*
  * Kernel timing (tracing).  While profiling is on for the calling thread, every kernel the
  * compute calls launch is bracketed by two hipEvents recorded on the launch stream, and the
  * tracker kernels also count the eval+solves they perform.  hom_profile_read waits for those

@@ -35,8 +35,8 @@ PREDICT_EULER, PREDICT_HERMITE, PREDICT_RK4 = 0, 1, 2
 
 EXPORTED = ["hom_create", "hom_create_batch", "hom_destroy", "hom_system_info", "hom_eval", "hom_step",
             "hom_step_proj", "hom_track_params_default", "hom_track", "hom_track_noalloc",
-            "hom_endpoint_grad", "hom_binomial_starts", "hom_set_profiling", "hom_profile_read",
-            "hom_last_error"]
+            "hom_endpoint_grad", "hom_binomial_starts", "hom_peak_probe", "hom_set_profiling",
+            "hom_profile_read", "hom_last_error"]
 
 
 class HomError(RuntimeError):
@@ -80,6 +80,7 @@ def _load():
     lib.hom_track_noalloc.argtypes = [P, P, i64, P, P, P, ctypes.POINTER(TrackParams), P, P, P]
     lib.hom_endpoint_grad.argtypes = [P, P, i64, P, P, P, i32, P]
     lib.hom_binomial_starts.argtypes = [i32, i32, P, P, P, P, P, P, i64, P]
+    lib.hom_peak_probe.argtypes = [i32, P, P]
     lib.hom_set_profiling.argtypes = [i32]
     lib.hom_profile_read.argtypes = [P, P, P, i32]
     lib.hom_last_error.restype = ctypes.c_char_p
@@ -265,6 +266,21 @@ def binomial_starts(D, beta, first=None, count=None, device="cuda"):
     if rows:
         _check(lib.hom_binomial_starts(*args, _ptr(z), rows, _stream()))
     return z, num
+
+
+PEAK_KINDS = {"hbm_read_gb_s": 0, "hbm_write_gb_s": 1, "fp64_fma_tflops": 2, "fp32_fma_tflops": 3,
+              "fp32_exp2_g_per_s": 4, "mfma_f64_tflops": 5, "mfma_bf16_tflops": 6,
+              "exp_f64_g_per_s": 7, "sincos_f64_g_per_s": 8}
+
+
+def peak_probes():
+    """Measured rates of the device's units (hom_peak_probe), keyed as PEAK_KINDS."""
+    out = {}
+    for name, kind in PEAK_KINDS.items():
+        v = ctypes.c_double()
+        _check(lib.hom_peak_probe(kind, ctypes.byref(v), _stream()))
+        out[name] = v.value
+    return out
 
 
 @dataclasses.dataclass

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhom.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["hom_api.hip", "k_eval.hip", "k_track.hip", "k_grad.hip", "k_dense.hip", "k_proj.hip",
-           "k_start.hip"]
+           "k_start.hip", "k_peak.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

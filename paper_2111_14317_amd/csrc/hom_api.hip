@@ -327,6 +327,15 @@ int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *be
   return HOM_OK;
 }
 
+int hom_peak_probe(int kind, double *rate, hom_stream_t stream) {
+  g_err.clear();
+  if (!rate) HOM_FAIL(HOM_EINVAL, "hom_peak_probe: NULL rate");
+  if (kind < HOM_PEAK_HBM_READ || kind > HOM_PEAK_SINCOS_F64)
+    HOM_FAIL(HOM_EINVAL, "hom_peak_probe: unknown kind");
+  HOM_HIP(peak_probe(kind, rate, (hipStream_t)stream), "hom_peak_probe");
+  return HOM_OK;
+}
+
 int hom_set_profiling(int on) {
   g_err.clear();
   if (on && !g_units_pool)

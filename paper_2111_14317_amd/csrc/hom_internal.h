@@ -191,6 +191,7 @@ std::string start_plan(int n, const int32_t *D, const double *beta, StartPlan *o
 void start_pack(int n, const std::vector<StartPlan> &plans, const int64_t *first,
                 const int64_t *count, std::vector<StartHdr> &hdr, std::vector<int64_t> &data,
                 int64_t *rows);
+hipError_t peak_probe(int kind, double *rate, hipStream_t stream);
 hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *data,
                                   int64_t rows, double *z, hipStream_t stream);
 
