@@ -217,3 +217,34 @@ def test_global_table_track(hom):
     ok = _np(a.status) == 0
     assert ok.mean() >= 0.9
     assert oracle.residual(csys, csys.c, _np(a.z)[ok]).max() <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["valu-n3", "bf16x3-n20"])
+def test_eval_flags_fp32(hom, which):
+    """HOM_UNSCALED and HOM_AFFINE with the FP32 evaluation: the vector-unit kernel (c1 shape, n = 3)
+    and the BF16x3 matrix-core engine (ragged n = 20, liftings up to 3), componentwise against the
+    oracle's unscaled values at the FP32 tolerance (1e-5 of each entry's term mass, floored at
+    1e-30 of the row's total as in the scaled comparison)."""
+    say(f"[eval flags fp32] {which}")
+    if which == "valu-n3":
+        sys, z, s = W.config_system("c1", P=257)
+    else:
+        sys, z, s = _ragged(lift=3)
+    h = hom.System.from_workload(sys)
+    n = sys.n
+    Go, _ = oracle.eval(sys, sys.c, z, s, scaled=False)
+    _, _, den = oracle.eval(sys, sys.c, z, s, with_den=True, scaled=False)
+    for affine in (False, True):
+        flags = hom.EVAL_FP32 | hom.UNSCALED | (hom.AFFINE if affine else 0)
+        G, L = hom.eval(h, sys.c, z, s, flags=flags)
+        assert np.all(_np(L) == 0)
+        ref, scale = Go.copy(), den.copy()
+        if affine:
+            ref[:, :, :n] *= np.exp(-z)[:, None, :]
+            ref[:, :, n] *= np.exp(-s)[:, None]
+            scale[:, :, :n] *= np.abs(np.exp(-z))[:, None, :]
+            scale[:, :, n] *= np.exp(-s)[:, None]
+        scale = np.maximum(scale, 1e-30 * scale[:, :, -1:])
+        err = np.abs(_np(G) - ref) / np.where(scale > 0, scale, 1.0)
+        say(f"  affine={affine}: max {err.max():.2e}")
+        assert err.max() <= 1e-5

@@ -112,3 +112,29 @@ def test_union_full_size_sampled(hom):
     err = eval_err(Gs, Ls, Go, Lo, den)
     say(f"  max scaled err {err.max():.3e}")
     assert err.max() <= 1e-12
+
+
+def test_union_eval_flags(hom):
+    """HOM_UNSCALED and HOM_AFFINE on the common-support engine (liftings up to 3, so that t^w
+    stays in range): the unscaled rows and J_x = J_z diag(e^{-z}), H_t = e^{-s} H_s against the
+    oracle, componentwise."""
+    say("[union eval flags] n=12 m=40 unscaled/affine")
+    rng = np.random.default_rng(17)
+    sys_ = W.union_system(12, 40, W._uniform_exps(-2, 2), "unit", 3, rng, rng, rng)
+    z, s = W.random_points(12, 45, rng, s_lo=-2.0)
+    h = hom.System.from_workload(sys_)
+    Go, _ = oracle.eval(sys_, sys_.c, z, s, scaled=False)
+    _, _, den = oracle.eval(sys_, sys_.c, z, s, with_den=True, scaled=False)
+    (Gu, Lu), eng = _engines(hom, h, lambda: hom.eval(h, sys_.c, z, s, flags=hom.UNSCALED))
+    assert "k_union<fp64>" in eng
+    assert np.all(_np(Lu) == 0)
+    assert (np.abs(_np(Gu) - Go) / np.where(den > 0, den, 1)).max() <= 1e-12
+    Ga, _ = hom.eval(h, sys_.c, z, s, flags=hom.UNSCALED | hom.AFFINE)
+    Ga, n = _np(Ga), sys_.n
+    ref = Go.copy()
+    ref[:, :, :n] *= np.exp(-z)[:, None, :]
+    ref[:, :, n] *= np.exp(-s)[:, None]
+    scale = den.copy()
+    scale[:, :, :n] *= np.abs(np.exp(-z))[:, None, :]
+    scale[:, :, n] *= np.exp(-s)[:, None]
+    assert (np.abs(Ga - ref) / np.where(scale > 0, scale, 1)).max() <= 1e-12
