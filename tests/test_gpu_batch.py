@@ -75,6 +75,35 @@ def test_batch_equals_single_system_runs(hom, prec):
         row += P
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_rk4_equals_single_system_runs(hom, prec):
+    """The Runge-Kutta predictor in the batched form: statuses equal to single-system runs with the
+    same predictor (FP64: endpoints bitwise, and path by path against the oracle's tracker with
+    that predictor)."""
+    say(f"[batch rk4] 8 systems, one launch, {prec}")
+    systems, starts, z, idx, c = _batch()
+    precision = hom.FP64 if prec == "fp64" else hom.MIXED
+    params = hom.default_params(precision, predictor=hom.PREDICT_RK4)
+    b = hom.Batch(systems)
+    st = hom.track(b, c, z, -32.0, params, sys_idx=idx)
+    zb, sb = _np(st.z), _np(st.status)
+    row = 0
+    for q, (sy, z0) in enumerate(zip(systems, starts)):
+        P = len(z0)
+        if P == 0:
+            continue
+        got = zb[row:row + P, :sy.n]
+        h = hom.System.from_workload(sy)
+        ref = hom.track(h, sy.c, z0, -32.0, params)
+        assert np.array_equal(_np(ref.status), sb[row:row + P])
+        if prec == "fp64":
+            assert np.array_equal(_np(ref.z), got)
+            ze, _, _, ost, _ = oracle.track(sy, sy.c, z0, -32.0, oracle.TrackParams(predictor=2))
+            check_fp64_per_path(sy, got, sb[row:row + P], ze, ost, f"system {q}",
+                                max_excluded=0.05)
+        row += P
+
+
 def test_batch_rejects_bad_use(hom):
     say("[batch] argument checks")
     systems, starts, z, idx, c = _batch(specs=((3, 4, 8), (4, 5, 8)))
