@@ -830,8 +830,14 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
   } else if (S.union_support) {  // common support: the exponentials once per point
     const size_t lds = kUnionCoefBytes + (size_t)S.union_tiles * 4 * 64 * 16;
     const int64_t tiles = (p1 - p0 + 15) / 16;
-    const int64_t per_cu = (int64_t)(kCuLdsBytes / lds) < 8 ? (int64_t)(kCuLdsBytes / lds) : 8;
-    const int64_t cap = (int64_t)num_cus() * (per_cu > 0 ? per_cu : 1);
+    // exactly the blocks that are resident at once (registers or LDS, whichever binds): every
+    // block strides over the same number of tiles, and none waits for a slot
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, S.dense.nct == 1 ? k_union_f64<OutT, 1> : k_union_f64<OutT, 2>, kUnionBlock,
+            lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    const int64_t cap = (int64_t)num_cus() * per_cu;
     const dim3 gu((unsigned)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap));
     if (S.dense.nct == 1)
       hipLaunchKernelGGL((k_union_f64<OutT, 1>), gu, dim3(kUnionBlock), lds, stream, S.dense, Cd,
