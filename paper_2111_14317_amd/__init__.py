@@ -260,7 +260,7 @@ def binomial_starts(D, beta, first=None, count=None, device="cuda"):
             f.ctypes.data_as(ctypes.c_void_p) if f is not None else None,
             c.ctypes.data_as(ctypes.c_void_p) if c is not None else None,
             num.ctypes.data_as(ctypes.c_void_p))
-    _check(lib.hom_binomial_starts(*args, None, 0, None))  # sizing: num_roots only
+    _check(lib.hom_binomial_starts(*args, None, 0, _stream()))  # sizing: num_roots only
     rows = int(c.sum()) if c is not None else int(num.sum())
     z = torch.empty((rows, n), dtype=torch.complex128, device=device)
     if rows:

@@ -290,40 +290,71 @@ int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *be
   if (!D || !beta || !num_roots) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: NULL array");
   if ((first == nullptr) != (count == nullptr))
     HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: first and count must both be given or both NULL");
-  std::vector<StartPlan> plans(num_cells);
-  for (int c = 0; c < num_cells; ++c) {
-    int code = HOM_EINVAL;
-    const std::string why = start_plan(n, D + (size_t)c * n * n, beta + (size_t)c * 2 * n,
-                                       &plans[c], &code);
-    if (!why.empty())
-      HOM_FAIL(code, "hom_binomial_starts: cell " + std::to_string(c) + ": " + why);
-    num_roots[c] = plans[c].det;
-    if (first && (first[c] < 0 || count[c] < 0 || first[c] > plans[c].det ||
-                  count[c] > plans[c].det - first[c]))
-      HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: cell " + std::to_string(c) +
-                               ": [first, first + count) outside its roots");
-  }
-  if (!z) return HOM_OK;
-  std::vector<StartHdr> hdr;
-  std::vector<int64_t> data;
-  int64_t rows = 0;
-  start_pack(n, plans, first, count, hdr, data, &rows);
-  if (rows > z_rows) HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: more roots than z_rows");
-  if (rows == 0) return HOM_OK;
   hipStream_t st = (hipStream_t)stream;
-  const size_t hb = hdr.size() * sizeof(StartHdr), db = data.size() * 8;
+  const int64_t cells = num_cells, rw = start_record_words(n), ww = start_ws_words(n);
+  int64_t ws_cells = ((int64_t)256 << 20) / (ww * 8);  // working arrays: at most 256 MiB
+  if (ws_cells > cells) ws_cells = cells;
+  if (ws_cells < 1) ws_cells = 1;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bD = up((size_t)cells * n * n * 4), bB = up((size_t)cells * 2 * n * 8),
+               bR = up((size_t)cells * rw * 8), bS = up((size_t)cells * 4), bT = up((size_t)cells * 8),
+               bW = up((size_t)ws_cells * ww * 8), bH = up((size_t)cells * sizeof(StartHdr));
   char *ws = nullptr;
-  HOM_HIP(hipMallocAsync((void **)&ws, hb + db + 8, st), "hom_binomial_starts: workspace");
-  hipError_t e = hipMemcpyAsync(ws, hdr.data(), hb, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && db)
-    e = hipMemcpyAsync(ws + hb, data.data(), db, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host tables die with this call
+  HOM_HIP(hipMallocAsync((void **)&ws, bD + bB + bR + bS + bT + bW + bH, st),
+          "hom_binomial_starts: workspace");
+  int32_t *dD = reinterpret_cast<int32_t *>(ws);
+  double *dB = reinterpret_cast<double *>(ws + bD);
+  int64_t *dR = reinterpret_cast<int64_t *>(ws + bD + bB);
+  int32_t *dS = reinterpret_cast<int32_t *>(ws + bD + bB + bR);
+  int64_t *dT = reinterpret_cast<int64_t *>(ws + bD + bB + bR + bS);
+  int64_t *dW = reinterpret_cast<int64_t *>(ws + bD + bB + bR + bS + bT);
+  StartHdr *dH = reinterpret_cast<StartHdr *>(ws + bD + bB + bR + bS + bT + bW);
+  std::vector<int32_t> hs(cells);
+  std::vector<StartHdr> hdr;
+  // plan every cell on the GPU, then read back each cell's status and root count
+  hipError_t e = hipMemcpyAsync(dD, D, (size_t)cells * n * n * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = launch_binomial_starts(n, num_cells, reinterpret_cast<const StartHdr *>(ws),
-                               reinterpret_cast<const int64_t *>(ws + hb), rows, z, st);
+    e = hipMemcpyAsync(dB, beta, (size_t)cells * 2 * n * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_start_plan(n, cells, dD, dB, dR, dS, dT, dW, ws_cells, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hs.data(), dS, (size_t)cells * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(num_roots, dT, (size_t)cells * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  std::string why;
+  int code = HOM_OK;
+  int64_t rows = 0;
+  for (int64_t c = 0; c < cells && e == hipSuccess && code == HOM_OK; ++c) {
+    if (hs[c] != 0) {
+      code = start_status_code(hs[c]);
+      why = "cell " + std::to_string(c) + ": " + start_status_text(hs[c]);
+    } else if (first && (first[c] < 0 || count[c] < 0 || first[c] > num_roots[c] ||
+                         count[c] > num_roots[c] - first[c])) {
+      code = HOM_EINVAL;
+      why = "cell " + std::to_string(c) + ": [first, first + count) outside its roots";
+    }
+  }
+  if (e == hipSuccess && code == HOM_OK && z) {
+    hdr.resize(cells);
+    for (int64_t c = 0; c < cells; ++c) {
+      hdr[c] = StartHdr{rows, first ? first[c] : 0, first ? count[c] : num_roots[c]};
+      rows += hdr[c].count;
+    }
+    if (rows > z_rows) {
+      code = HOM_EINVAL;
+      why = "more roots than z_rows";
+    } else if (rows > 0) {
+      e = hipMemcpyAsync(dH, hdr.data(), (size_t)cells * sizeof(StartHdr), hipMemcpyHostToDevice,
+                         st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host headers die with this call
+      if (e == hipSuccess)
+        e = launch_binomial_starts(n, num_cells, dH, dR, rows, z, st);
+    }
+  }
   hipError_t e2 = hipFreeAsync(ws, st);
   HOM_HIP(e, "hom_binomial_starts");
   HOM_HIP(e2, "hom_binomial_starts: free workspace");
+  if (code != HOM_OK) HOM_FAIL(code, "hom_binomial_starts: " + why);
   return HOM_OK;
 }
 

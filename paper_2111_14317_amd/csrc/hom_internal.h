@@ -172,27 +172,25 @@ hipError_t launch_step_proj(const System &S, const void *cws, const double *c, i
 // number of compute units of the current device (cached)
 int num_cus();
 
-// Start points (k_start.hip): one binomial cell's plan (host) and its device header.
-struct StartPlan {
-  int64_t det = 0, L = 1;       // |det D| and the largest invariant factor
-  std::vector<int64_t> sig;     // invariant factors above one
-  std::vector<int64_t> cm;      // [sig.size()][n]: (V_il mod sig_l) * (L / sig_l) mod L
-  std::vector<double> zb;       // z_base = D^{-1} log(beta), complex [n]
-};
+// Start points (k_start.hip).  Per cell of n unknowns: a plan record of start_record_words(n)
+// int64 words (L, the count of invariant factors above one, z_base, their radices and V
+// columns) and, while planning, start_ws_words(n) words of working arrays.
+__host__ __device__ constexpr int64_t start_record_words(int n) {
+  return 2 + 2 * (int64_t)n + n + (int64_t)n * n;
+}
+__host__ __device__ constexpr int64_t start_ws_words(int n) { return 3 * (int64_t)n * n + 3 * n; }
 struct StartHdr {
   int64_t row0;   // first output row of the cell
   int64_t first;  // first root index
   int64_t count;  // roots written
-  int64_t L;
-  int64_t off;    // offset of the cell's data (int64 words)
-  int32_t nlive, pad;
 };
-std::string start_plan(int n, const int32_t *D, const double *beta, StartPlan *out, int *code);
-void start_pack(int n, const std::vector<StartPlan> &plans, const int64_t *first,
-                const int64_t *count, std::vector<StartHdr> &hdr, std::vector<int64_t> &data,
-                int64_t *rows);
-hipError_t peak_probe(int kind, double *rate, hipStream_t stream);
-hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *data,
+hipError_t peak_probe(int kind, double *rate, hipStream_t stream);  // k_peak.hip
+const char *start_status_text(int32_t status);  // "" for a cell planned without error
+int start_status_code(int32_t status);          // HOM_EINVAL or HOM_EUNSUPPORTED
+hipError_t launch_start_plan(int n, int64_t num_cells, const int32_t *D, const double *beta,
+                             int64_t *rec, int32_t *status, int64_t *det, int64_t *ws,
+                             int64_t ws_cells, hipStream_t stream);
+hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *rec,
                                   int64_t rows, double *z, hipStream_t stream);
 
 }  // namespace hom

@@ -76,43 +76,20 @@ def test_default_params_match_oracle_defaults():
         assert getattr(p, f) == getattr(o, f), f
 
 
-def test_binomial_starts_sizing_and_errors_without_gpu():
-    """hom_binomial_starts with z = NULL touches no GPU: |det D| per cell from the host Smith
-    form (against the oracle's root counts and numpy's determinant), and argument errors."""
+def test_binomial_starts_argument_errors_without_gpu():
+    """hom_binomial_starts refuses bad arguments before it touches the GPU."""
     import paper_2111_14317_amd as hom
-    import oracle
     lib = hom.lib
     P = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
-    rng = np.random.default_rng(12)
-    cells, dets = [], []
-    for n in (1, 2, 3, 4, 6):
-        while True:
-            D = rng.integers(-3, 4, size=(n, n)).astype(np.int32)
-            d = round(abs(np.linalg.det(D)))
-            if 0 < d <= 200:
-                break
-        beta = rng.normal(size=n) + 1j * rng.normal(size=n)
-        num = np.zeros(1, np.int64)
-        assert lib.hom_binomial_starts(n, 1, P(D), P(beta), None, None, P(num), None, 0,
-                                       None) == hom.HOM_OK
-        assert num[0] == d == len(oracle.binomial_roots(D, beta))
-    # a batch of cells of one size
-    D = np.stack([np.diag([2, 3]), np.array([[1, 2], [3, 4]]), np.array([[4, 0], [0, -1]])]).astype(np.int32)
-    beta = np.ones((3, 2), np.complex128)
-    num = np.zeros(3, np.int64)
-    assert lib.hom_binomial_starts(2, 3, P(D), P(beta), None, None, P(num), None, 0, None) == 0
-    assert list(num) == [6, 2, 4]
+    D = np.array([[[2, 0], [0, 3]]], np.int32)
+    beta = np.ones((1, 2), np.complex128)
+    num = np.zeros(1, np.int64)
     E = hom.HOM_EINVAL
-    sing = np.array([[[1, 2], [2, 4]]], np.int32)
-    assert lib.hom_binomial_starts(2, 1, P(sing), P(beta[:1]), None, None, P(num), None, 0, None) == E
-    assert b"singular" in lib.hom_last_error()
-    zero = np.array([[1.0, 0.0]], np.complex128)
-    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(zero), None, None, P(num), None, 0, None) == E
-    assert lib.hom_binomial_starts(0, 1, P(D[:1]), P(beta), None, None, P(num), None, 0, None) == E
-    assert lib.hom_binomial_starts(33, 1, P(D[:1]), P(beta), None, None, P(num), None, 0, None) == E
-    f, c = np.array([0], np.int64), np.array([7], np.int64)  # 7 > 6 roots
-    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(beta), P(f), P(c), P(num), None, 0, None) == E
-    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(beta), P(f), None, P(num), None, 0, None) == E
-    big = np.array([[[65536, 0], [0, 32769]]], np.int32)  # invariant factors 1, 65536 * 32769
-    assert lib.hom_binomial_starts(2, 1, P(big), P(beta), None, None, P(num), None, 0,
-                                   None) == hom.HOM_EUNSUPPORTED
+    assert lib.hom_binomial_starts(0, 1, P(D), P(beta), None, None, P(num), None, 0, None) == E
+    assert lib.hom_binomial_starts(33, 1, P(D), P(beta), None, None, P(num), None, 0, None) == E
+    assert lib.hom_binomial_starts(2, 0, P(D), P(beta), None, None, P(num), None, 0, None) == E
+    assert lib.hom_binomial_starts(2, 1, None, P(beta), None, None, P(num), None, 0, None) == E
+    assert lib.hom_binomial_starts(2, 1, P(D), P(beta), None, None, None, None, 0, None) == E
+    f = np.array([0], np.int64)
+    assert lib.hom_binomial_starts(2, 1, P(D), P(beta), P(f), None, P(num), None, 0, None) == E
+    assert b"first and count" in lib.hom_last_error()

@@ -146,3 +146,43 @@ def test_full_size_cell_properties(hom):
     L = int(sig[-1])
     lat = np.mod(np.rint((zn.imag - zn[:1].imag) / (2 * np.pi) * L).astype(np.int64), L)
     assert len(np.unique(lat, axis=0)) == len(zn)
+
+
+def test_plan_counts_and_errors(hom):
+    """The GPU plan's root counts equal |det D| (numpy) and the oracle's; singular D, zero beta,
+    a range outside a cell's roots and too few output rows are refused (HOM_EINVAL); a largest
+    invariant factor beyond 2^31 is HOM_EUNSUPPORTED."""
+    import ctypes
+    import torch
+    lib = hom.lib
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+    rng = np.random.default_rng(12)
+    for n in (1, 2, 3, 4, 6):
+        D, beta = _cell(rng, n, 200)
+        D = np.ascontiguousarray(D, np.int32)
+        beta = np.ascontiguousarray(beta)
+        num = np.zeros(1, np.int64)
+        assert lib.hom_binomial_starts(n, 1, P(D), P(beta), None, None, P(num), None, 0,
+                                       None) == hom.HOM_OK
+        assert num[0] == round(abs(np.linalg.det(D))) == len(oracle.binomial_roots(D, beta))
+    D = np.stack([np.diag([2, 3]), np.array([[1, 2], [3, 4]]), np.array([[4, 0], [0, -1]])]).astype(np.int32)
+    beta = np.ones((3, 2), np.complex128)
+    num = np.zeros(3, np.int64)
+    assert lib.hom_binomial_starts(2, 3, P(D), P(beta), None, None, P(num), None, 0, None) == 0
+    assert list(num) == [6, 2, 4]
+    E = hom.HOM_EINVAL
+    sing = np.array([[[1, 2], [2, 4]]], np.int32)
+    assert lib.hom_binomial_starts(2, 1, P(sing), P(beta[:1]), None, None, P(num), None, 0, None) == E
+    assert b"singular" in lib.hom_last_error()
+    zero = np.array([[1.0, 0.0]], np.complex128)
+    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(zero), None, None, P(num), None, 0, None) == E
+    assert b"beta" in lib.hom_last_error()
+    f, c = np.array([0], np.int64), np.array([7], np.int64)  # 7 > 6 roots
+    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(beta), P(f), P(c), P(num), None, 0, None) == E
+    z = torch.zeros((5, 2), dtype=torch.complex128, device="cuda")  # 6 roots, 5 rows
+    zp = ctypes.c_void_p(z.data_ptr())
+    assert lib.hom_binomial_starts(2, 1, P(D[:1]), P(beta), None, None, P(num), zp, 5, None) == E
+    assert b"z_rows" in lib.hom_last_error()
+    big = np.array([[[65536, 0], [0, 32769]]], np.int32)  # invariant factors 1, 65536 * 32769
+    assert lib.hom_binomial_starts(2, 1, P(big), P(beta), None, None, P(num), None, 0,
+                                   None) == hom.HOM_EUNSUPPORTED
