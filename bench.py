@@ -345,6 +345,7 @@ def run_starts(hom, torch, reps=3):
     """Start points of the n = 10 tracking workload's planted cell: all |det D| = 3,881,632 roots
     of its binomial system (host Smith form, then one GPU launch writing 16 bytes per root
     coordinate, judged against HBM)."""
+    import numpy as np
     import workloads as W
     csys, cell, _ = W.planted_config("c2", P=4)
     D, beta = W.cell_binomial(csys, cell)
@@ -360,14 +361,49 @@ def run_starts(hom, torch, reps=3):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / reps
     hom.set_profiling(False)
-    ms = sum(t for k, t, _ in hom.profile_read() if k == "k_binomial_starts") / reps
+    prof = hom.profile_read()
+    ms = sum(t for k, t, _ in prof if k == "k_binomial_starts") / reps
+    plan_ms = sum(t for k, t, _ in prof if k == "k_start_plan") / reps
     rows = int(num[0])
     nbytes = rows * csys.n * 16
-    rec = {"roots": rows, "n": csys.n, "kernel_ms": ms, "call_ms": wall * 1e3,
+    rec = {"roots": rows, "n": csys.n, "kernel_ms": ms, "plan_ms": plan_ms, "call_ms": wall * 1e3,
            "roots_per_s": rows / (ms * 1e-3), "hbm_gb_per_s": nbytes / (ms * 1e-3) / 1e9,
            "frac_of_hbm_peak": nbytes / (ms * 1e-3) / PEAK_HBM}
     print(f"# starts n=10 cell: {rows} roots, kernel {ms:.3f} ms ({rec['hbm_gb_per_s']:.0f} GB/s), "
-          f"call {wall * 1e3:.2f} ms", file=sys.stderr, flush=True)
+          f"plan {plan_ms:.2f} ms, call {wall * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    # many cells in one call: 1024 n = 10 cells (random exponent differences in [-3, 3] with
+    # 1 <= |det| <= 64), every root: the plan is one GPU thread per cell
+    rng = np.random.default_rng(2111)
+    Ds, betas = [], []
+    while len(Ds) < 1024:
+        Dc = rng.integers(-3, 4, size=(10, 10))
+        Dc = np.triu(Dc, 1) * (rng.random((10, 10)) < 0.2) + np.diag(rng.choice([1, 1, 2, 3], 10))
+        Dc = (np.tril(rng.integers(-1, 2, size=(10, 10)) * (rng.random((10, 10)) < 0.2), -1)
+              + np.eye(10, dtype=np.int64)) @ Dc
+        d = round(abs(np.linalg.det(Dc)))
+        if 1 <= d <= 64:
+            Ds.append(Dc[rng.permutation(10)])
+            betas.append(rng.normal(size=10) + 1j * rng.normal(size=10))
+    Ds, betas = np.stack(Ds), np.stack(betas)
+    z, num = hom.binomial_starts(Ds, betas)
+    del z
+    torch.cuda.synchronize()
+    hom.profile_read()
+    hom.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        z, _ = hom.binomial_starts(Ds, betas)
+        del z
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    hom.set_profiling(False)
+    prof = hom.profile_read()
+    rec["batch_1024_cells_n10"] = {
+        "roots": int(num.sum()),
+        "plan_ms": sum(t for k, t, _ in prof if k == "k_start_plan") / reps,
+        "kernel_ms": sum(t for k, t, _ in prof if k == "k_binomial_starts") / reps,
+        "call_ms": wall * 1e3}
+    print(f"# starts 1024 n=10 cells: {rec['batch_1024_cells_n10']}", file=sys.stderr, flush=True)
     return rec
 
 

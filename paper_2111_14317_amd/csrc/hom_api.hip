@@ -291,31 +291,27 @@ int hom_binomial_starts(int n, int num_cells, const int32_t *D, const double *be
   if ((first == nullptr) != (count == nullptr))
     HOM_FAIL(HOM_EINVAL, "hom_binomial_starts: first and count must both be given or both NULL");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t cells = num_cells, rw = start_record_words(n), ww = start_ws_words(n);
-  int64_t ws_cells = ((int64_t)256 << 20) / (ww * 8);  // working arrays: at most 256 MiB
-  if (ws_cells > cells) ws_cells = cells;
-  if (ws_cells < 1) ws_cells = 1;
+  const int64_t cells = num_cells, rw = start_record_words(n);
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t bD = up((size_t)cells * n * n * 4), bB = up((size_t)cells * 2 * n * 8),
                bR = up((size_t)cells * rw * 8), bS = up((size_t)cells * 4), bT = up((size_t)cells * 8),
-               bW = up((size_t)ws_cells * ww * 8), bH = up((size_t)cells * sizeof(StartHdr));
+               bH = up((size_t)cells * sizeof(StartHdr));
   char *ws = nullptr;
-  HOM_HIP(hipMallocAsync((void **)&ws, bD + bB + bR + bS + bT + bW + bH, st),
+  HOM_HIP(hipMallocAsync((void **)&ws, bD + bB + bR + bS + bT + bH, st),
           "hom_binomial_starts: workspace");
   int32_t *dD = reinterpret_cast<int32_t *>(ws);
   double *dB = reinterpret_cast<double *>(ws + bD);
   int64_t *dR = reinterpret_cast<int64_t *>(ws + bD + bB);
   int32_t *dS = reinterpret_cast<int32_t *>(ws + bD + bB + bR);
   int64_t *dT = reinterpret_cast<int64_t *>(ws + bD + bB + bR + bS);
-  int64_t *dW = reinterpret_cast<int64_t *>(ws + bD + bB + bR + bS + bT);
-  StartHdr *dH = reinterpret_cast<StartHdr *>(ws + bD + bB + bR + bS + bT + bW);
+  StartHdr *dH = reinterpret_cast<StartHdr *>(ws + bD + bB + bR + bS + bT);
   std::vector<int32_t> hs(cells);
   std::vector<StartHdr> hdr;
   // plan every cell on the GPU, then read back each cell's status and root count
   hipError_t e = hipMemcpyAsync(dD, D, (size_t)cells * n * n * 4, hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dB, beta, (size_t)cells * 2 * n * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_start_plan(n, cells, dD, dB, dR, dS, dT, dW, ws_cells, st);
+  if (e == hipSuccess) e = launch_start_plan(n, cells, dD, dB, dR, dS, dT, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hs.data(), dS, (size_t)cells * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess)

@@ -172,13 +172,12 @@ hipError_t launch_step_proj(const System &S, const void *cws, const double *c, i
 // number of compute units of the current device (cached)
 int num_cus();
 
-// Start points (k_start.hip).  Per cell of n unknowns: a plan record of start_record_words(n)
-// int64 words (L, the count of invariant factors above one, z_base, their radices and V
-// columns) and, while planning, start_ws_words(n) words of working arrays.
+// Start points (k_start.hip).  Per cell of n unknowns (n <= 32): a plan record of
+// start_record_words(n) int64 words (L, the count of invariant factors above one, z_base, their
+// radices and V columns).
 __host__ __device__ constexpr int64_t start_record_words(int n) {
   return 2 + 2 * (int64_t)n + n + (int64_t)n * n;
 }
-__host__ __device__ constexpr int64_t start_ws_words(int n) { return 3 * (int64_t)n * n + 3 * n; }
 struct StartHdr {
   int64_t row0;   // first output row of the cell
   int64_t first;  // first root index
@@ -188,8 +187,7 @@ hipError_t peak_probe(int kind, double *rate, hipStream_t stream);  // k_peak.hi
 const char *start_status_text(int32_t status);  // "" for a cell planned without error
 int start_status_code(int32_t status);          // HOM_EINVAL or HOM_EUNSUPPORTED
 hipError_t launch_start_plan(int n, int64_t num_cells, const int32_t *D, const double *beta,
-                             int64_t *rec, int32_t *status, int64_t *det, int64_t *ws,
-                             int64_t ws_cells, hipStream_t stream);
+                             int64_t *rec, int32_t *status, int64_t *det, hipStream_t stream);
 hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *rec,
                                   int64_t rows, double *z, hipStream_t stream);
 

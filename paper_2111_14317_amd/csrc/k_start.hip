@@ -8,13 +8,15 @@
 // matters, so V is needed modulo the largest factor L = sigma_{n-1} (every sigma_l divides L):
 // column l contributes ((V_il mod sigma_l) * (L / sigma_l) * j_l mod L) / L.
 //
-// k_start_plan, one thread per cell: the Smith form by elementary operations on int64 with
-// overflow checks, run twice (the second run repeats the first one's operations and carries V
-// modulo the L the first run found), and z_base by an FP64 LU solve; it writes the cell's record.
+// k_start_plan, one wave per cell, its matrices in LDS: the Smith form by elementary operations
+// on int64 with overflow checks, the lanes splitting each row and column operation, run twice
+// (the second run repeats the first one's operations and carries V modulo the L the first run
+// found), and z_base by an FP64 LU solve; it writes the cell's record.
 // k_binomial_starts, one thread per (root, coordinate): the root from its record, writing
 // consecutive doubles, so the launch streams its output to HBM.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 
 #include "hom_internal.h"
@@ -37,187 +39,248 @@ __device__ __forceinline__ bool fma_ok(int64_t &dst, int64_t f, int64_t src) {  
   dst = r;
   return true;
 }
-__device__ __forceinline__ int64_t abs64(int64_t v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int64_t mod_pos(int64_t v, int64_t m) {
   const int64_t r = v % m;
   return r < 0 ? r + m : r;
 }
 
-// Smith form of the n x n matrix M (row-major, int64, destroyed): the invariant factors in
-// sig[0..n).  With V (n x n), V is carried modulo L (column operations only; entries in [0, L)).
-__device__ int32_t smith64(int n, int64_t *M, int64_t *V, int64_t L, int64_t *sig) {
-  auto at = [&](int i, int j) -> int64_t & { return M[i * n + j]; };
-  if (V)
-    for (int i = 0; i < n * n; ++i) V[i] = (i / n == i % n) ? mod_pos(1, L) : 0;
-  for (int t = 0; t < n; ++t) {
-    int round = 0;
-    for (;; ++round) {
-      if (round >= kSmithRounds) return kPlanOverflow;
-      int bi = -1, bj = -1;  // smallest nonzero |entry| of the trailing block, first in row order
-      for (int i = t; i < n; ++i)
-        for (int j = t; j < n; ++j)
-          if (at(i, j) != 0 && (bi < 0 || abs64(at(i, j)) < abs64(at(bi, bj)))) {
-            bi = i;
-            bj = j;
-          }
-      if (bi < 0) return kPlanSingular;
-      if (bi != t)
-        for (int j = 0; j < n; ++j) {
-          const int64_t a = at(t, j);
-          at(t, j) = at(bi, j);
-          at(bi, j) = a;
-        }
-      if (bj != t) {
-        for (int i = 0; i < n; ++i) {
-          const int64_t a = at(i, t);
-          at(i, t) = at(i, bj);
-          at(i, bj) = a;
-        }
-        if (V)
-          for (int i = 0; i < n; ++i) {
-            const int64_t a = V[i * n + t];
-            V[i * n + t] = V[i * n + bj];
-            V[i * n + bj] = a;
-          }
-      }
-      bool done = true;
-      const int64_t p = at(t, t);
-      for (int i = t + 1; i < n; ++i) {  // rows below: row i -= q row t
-        const int64_t q = at(i, t) / p;
-        if (q != 0)
-          for (int j = 0; j < n; ++j)
-            if (!fma_ok(at(i, j), -q, at(t, j))) return kPlanOverflow;
-        if (at(i, t) != 0) done = false;
-      }
-      for (int j = t + 1; j < n; ++j) {  // columns right: col j -= q col t (and in V)
-        const int64_t q = at(t, j) / p;
-        if (q != 0) {
-          for (int i = 0; i < n; ++i)
-            if (!fma_ok(at(i, j), -q, at(i, t))) return kPlanOverflow;
-          if (V) {
-            const int64_t qm = mod_pos(-q, L);
-            for (int i = 0; i < n; ++i)
-              V[i * n + j] = (V[i * n + j] + qm * V[i * n + t]) % L;
-          }
-        }
-        if (at(t, j) != 0) done = false;
-      }
-      if (!done) continue;
-      int bad = -1;  // the pivot must divide the whole trailing block
-      for (int i = t + 1; i < n && bad < 0; ++i)
-        for (int j = t + 1; j < n; ++j)
-          if (at(i, j) % p != 0) {
-            bad = i;
-            break;
-          }
-      if (bad < 0) break;
-      for (int j = 0; j < n; ++j)  // row t += row bad
-        if (!fma_ok(at(t, j), 1, at(bad, j))) return kPlanOverflow;
+// Per-wave helpers of the plan: the block is one wave, so __syncthreads is the wave's barrier
+// (and memory fence) and every value that steers control flow below is wave-uniform.
+constexpr int kPlanMaxN = 32;
+
+// lexicographic minimum of (key, idx) over the wave, in every lane
+__device__ __forceinline__ void wave_min2(unsigned long long &key, int &idx) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long ok = __shfl_xor(key, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ok < key || (ok == key && oi < idx)) {
+      key = ok;
+      idx = oi;
     }
-    sig[t] = abs64(at(t, t));  // (a sign is a row operation: U only)
   }
+}
+__device__ __forceinline__ unsigned long long uabs64(int64_t v) {
+  return v < 0 ? 0ull - (unsigned long long)v : (unsigned long long)v;
+}
+
+// Smith form of the n x n matrix M (row-major, int64, in LDS, destroyed), one wave: the
+// invariant factors in sig[0..n).  With V (n x n int32 in LDS), V is carried modulo L (column
+// operations only; entries in [0, L), L < 2^31).  Per pivot position t: move the smallest nonzero
+// |entry| of the trailing block (the first in row order among equals) to (t, t); reduce the
+// entries below it and right of it by their quotients; repeat until both are zero, then, if the
+// pivot does not divide the whole trailing block, add the first row holding a non-multiple to
+// row t and repeat.  The lanes split each row or column operation; q is n words of scratch.
+__device__ int32_t smith_wave(int n, int64_t *M, int32_t *V, int64_t L, int64_t *q, int64_t *sig,
+                              int lane) {
+  if (V)
+    for (int e = lane; e < n * n; e += 64) V[e] = (e / n == e % n) ? 1 : 0;
+  __syncthreads();
+  for (int t = 0; t < n; ++t) {
+    const int w = n - t;  // trailing block: rows and columns t..n-1
+    for (int round = 0;; ++round) {
+      if (round >= kSmithRounds) return kPlanOverflow;
+      unsigned long long key = ~0ull;
+      int idx = INT_MAX;
+      for (int e = lane; e < w * w; e += 64) {
+        const int lin = (t + e / w) * n + t + e % w;  // row-major: increasing in row order
+        const int64_t v = M[lin];
+        if (v != 0 && uabs64(v) < key) {
+          key = uabs64(v);
+          idx = lin;
+        }
+      }
+      wave_min2(key, idx);
+      if (key == ~0ull) return kPlanSingular;
+      const int bi = idx / n, bj = idx % n;
+      if (bi != t && lane < n) {
+        const int64_t a = M[t * n + lane];
+        M[t * n + lane] = M[bi * n + lane];
+        M[bi * n + lane] = a;
+      }
+      __syncthreads();
+      if (bj != t && lane < n) {
+        const int64_t a = M[lane * n + t];
+        M[lane * n + t] = M[lane * n + bj];
+        M[lane * n + bj] = a;
+        if (V) {
+          const int32_t b = V[lane * n + t];
+          V[lane * n + t] = V[lane * n + bj];
+          V[lane * n + bj] = b;
+        }
+      }
+      __syncthreads();
+      const int64_t p = M[t * n + t];
+      const bool unit = p == 1 || p == -1;  // the common case: quotients without a division
+      // rows below: row i -= q_i row t
+      if (lane > t && lane < n) q[lane] = unit ? M[lane * n + t] * p : M[lane * n + t] / p;
+      __syncthreads();
+      bool ok = true;
+      for (int e = lane; e < (w - 1) * n; e += 64) {
+        const int i = t + 1 + e / n, j = e % n;
+        if (q[i] != 0) ok = ok && fma_ok(M[i * n + j], -q[i], M[t * n + j]);
+      }
+      if (__syncthreads_or(!ok)) return kPlanOverflow;
+      // columns right: col j -= q_j col t, and in V modulo L
+      if (lane > t && lane < n) q[lane] = unit ? M[t * n + lane] * p : M[t * n + lane] / p;
+      __syncthreads();
+      for (int e = lane; e < (w - 1) * n; e += 64) {
+        const int j = t + 1 + e / n, i = e % n;
+        const int64_t qj = q[j];
+        if (qj != 0) {
+          ok = ok && fma_ok(M[i * n + j], -qj, M[i * n + t]);
+          if (V)
+            V[i * n + j] = (int32_t)(((int64_t)V[i * n + j] + mod_pos(-qj, L) * V[i * n + t]) % L);
+        }
+      }
+      if (__syncthreads_or(!ok)) return kPlanOverflow;
+      const bool rest = lane > t && lane < n && (M[lane * n + t] != 0 || M[t * n + lane] != 0);
+      if (__syncthreads_or(rest)) continue;
+      if (unit) break;  // a unit divides the whole trailing block
+      int bad = INT_MAX;  // first row of the trailing block with an entry p does not divide
+      for (int e = lane; e < (w - 1) * (w - 1); e += 64) {
+        const int i = t + 1 + e / (w - 1), j = t + 1 + e % (w - 1);
+        if (M[i * n + j] % p != 0 && i < bad) bad = i;
+      }
+      unsigned long long bk = (unsigned long long)bad;
+      wave_min2(bk, bad);
+      if (bad == INT_MAX) break;
+      if (lane < n) ok = fma_ok(M[t * n + lane], 1, M[bad * n + lane]);  // row t += row bad
+      if (__syncthreads_or(!ok)) return kPlanOverflow;
+    }
+    if (lane == 0) sig[t] = (int64_t)uabs64(M[t * n + t]);  // (a sign is a row operation: U only)
+  }
+  __syncthreads();
   return kPlanOk;
 }
 
-// x = D^{-1} b for complex b (FP64 LU with partial pivoting on a copy A of D); false if singular
-__device__ bool solve_complex(int n, const int32_t *D, double *A, double *br, double *bi) {
-  for (int i = 0; i < n * n; ++i) A[i] = (double)D[i];
+// x = D^{-1} b for the complex right-hand side (br, bi) in place, one wave: FP64 LU with partial
+// pivoting (the largest |entry| of the column, the first among equals) on A (n x n in LDS), then
+// back substitution by columns; f is n doubles of scratch.  False if D is singular.
+__device__ bool solve_wave(int n, const int32_t *D, double *A, double *br, double *bi, double *f,
+                           int lane) {
+  for (int e = lane; e < n * n; e += 64) A[e] = (double)D[e];
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    int p = j;
-    for (int i = j + 1; i < n; ++i)
-      if (fabs(A[i * n + j]) > fabs(A[p * n + j])) p = i;
-    if (A[p * n + j] == 0.0) return false;
-    if (p != j) {
-      for (int k = 0; k < n; ++k) {
-        const double a = A[j * n + k];
-        A[j * n + k] = A[p * n + k];
-        A[p * n + k] = a;
+    // magnitudes are >= 0, so their bit patterns order like the values; complemented for a min
+    unsigned long long key = ~0ull;
+    int idx = INT_MAX;
+    if (lane >= j && lane < n) {
+      key = ~(unsigned long long)__double_as_longlong(fabs(A[lane * n + j]));
+      idx = lane;
+    }
+    wave_min2(key, idx);
+    if (key == ~0ull) return false;  // the whole column is zero
+    if (idx != j) {
+      if (lane < n) {
+        const double a = A[j * n + lane];
+        A[j * n + lane] = A[idx * n + lane];
+        A[idx * n + lane] = a;
       }
-      double a = br[j];
-      br[j] = br[p];
-      br[p] = a;
-      a = bi[j];
-      bi[j] = bi[p];
-      bi[p] = a;
+      if (lane == 0) {
+        double a = br[j];
+        br[j] = br[idx];
+        br[idx] = a;
+        a = bi[j];
+        bi[j] = bi[idx];
+        bi[idx] = a;
+      }
     }
-    for (int i = j + 1; i < n; ++i) {
-      const double f = A[i * n + j] / A[j * n + j];
-      for (int k = j; k < n; ++k) A[i * n + k] -= f * A[j * n + k];
-      br[i] -= f * br[j];
-      bi[i] -= f * bi[j];
+    __syncthreads();
+    if (lane > j && lane < n) f[lane] = A[lane * n + j] / A[j * n + j];
+    __syncthreads();
+    const int w = n - j;
+    for (int e = lane; e < (w - 1) * w; e += 64) {
+      const int i = j + 1 + e / w, k = j + e % w;
+      A[i * n + k] -= f[i] * A[j * n + k];
     }
+    if (lane > j && lane < n) {
+      br[lane] -= f[lane] * br[j];
+      bi[lane] -= f[lane] * bi[j];
+    }
+    __syncthreads();
   }
   for (int i = n - 1; i >= 0; --i) {
-    double vr = br[i], vi = bi[i];
-    for (int k = i + 1; k < n; ++k) {
-      vr -= A[i * n + k] * br[k];
-      vi -= A[i * n + k] * bi[k];
+    const double d = A[i * n + i], xr = br[i] / d, xi = bi[i] / d;
+    __syncthreads();
+    if (lane < i) {
+      br[lane] -= A[lane * n + i] * xr;
+      bi[lane] -= A[lane * n + i] * xi;
+    } else if (lane == i) {
+      br[i] = xr;
+      bi[i] = xi;
     }
-    br[i] = vr / A[i * n + i];
-    bi[i] = vi / A[i * n + i];
+    __syncthreads();
   }
   return true;
 }
 
-// One thread per cell of [c0, c1): status[c], det[c] and the record (start_record_words(n) int64
-// words): [0] L, [1] the number of invariant factors above one, then z_base (2n doubles), their
-// radices, then their V columns (n each).  ws: the thread's working arrays (start_ws_words(n)).
+// One wave (block) per cell, grid-stride: status[c], det[c] and the record
+// (start_record_words(n) int64 words): [0] L, [1] the number of invariant factors above one,
+// then z_base (2n doubles), their radices, then their V columns (n each).  The Smith form runs
+// twice: the first run finds the factors and L, the second repeats its operations (the same
+// matrix, so the same choices) and carries V modulo L.
 __global__ void __launch_bounds__(64)
-    k_start_plan(int n, int64_t c0, int64_t c1, const int32_t *__restrict__ Dall,
+    k_start_plan(int n, int64_t num_cells, const int32_t *__restrict__ Dall,
                  const double *__restrict__ beta_all, int64_t *__restrict__ rec_all,
-                 int32_t *__restrict__ status, int64_t *__restrict__ det_out,
-                 int64_t *__restrict__ ws_all) {
-  for (int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < c1;
-       c += (int64_t)gridDim.x * blockDim.x) {
+                 int32_t *__restrict__ status, int64_t *__restrict__ det_out) {
+  __shared__ int64_t sM[kPlanMaxN * kPlanMaxN];  // the Smith forms, then the LU (as doubles)
+  __shared__ int32_t sV[kPlanMaxN * kPlanMaxN];
+  __shared__ int64_t sQ[kPlanMaxN], sSig[kPlanMaxN];
+  __shared__ double sB[2 * kPlanMaxN];
+  const int lane = threadIdx.x;
+  double *sA = reinterpret_cast<double *>(sM), *sF = reinterpret_cast<double *>(sQ);
+  for (int64_t c = blockIdx.x; c < num_cells; c += gridDim.x) {
     const int32_t *D = Dall + c * n * n;
-    const double *beta = beta_all + c * 2 * n;
     int64_t *rec = rec_all + c * start_record_words(n);
-    int64_t *M = ws_all + (c - c0) * start_ws_words(n);
-    int64_t *V = M + n * n;
-    int64_t *sig = V + n * n;
-    double *A = reinterpret_cast<double *>(sig + n);
-    double *br = A + n * n, *bi = br + n;
-    det_out[c] = 0;
-    int32_t st = kPlanOk;
-    for (int k = 0; k < n; ++k) {
-      const double r = beta[2 * k], im = beta[2 * k + 1];
-      if (!isfinite(r) || !isfinite(im) || (r == 0.0 && im == 0.0)) st = kPlanBadBeta;
-      br[k] = log(hypot(r, im));
-      bi[k] = atan2(im, r);
+    bool bad_beta = false;
+    if (lane < n) {
+      const double r = beta_all[(c * n + lane) * 2], im = beta_all[(c * n + lane) * 2 + 1];
+      bad_beta = !isfinite(r) || !isfinite(im) || (r == 0.0 && im == 0.0);
+      sB[lane] = log(hypot(r, im));
+      sB[kPlanMaxN + lane] = atan2(im, r);
     }
-    for (int i = 0; i < n * n && st == kPlanOk; ++i) M[i] = D[i];
-    if (st == kPlanOk) st = smith64(n, M, nullptr, 1, sig);
+    for (int e = lane; e < n * n; e += 64) sM[e] = D[e];
+    int32_t st = __syncthreads_or(bad_beta) ? kPlanBadBeta : kPlanOk;
+    if (st == kPlanOk) st = smith_wave(n, sM, nullptr, 1, sQ, sSig, lane);
     int64_t det = 1;
     for (int l = 0; l < n && st == kPlanOk; ++l)
-      if (__builtin_mul_overflow(det, sig[l], &det) || det >= ((int64_t)1 << 62)) st = kPlanTooMany;
-    const int64_t L = st == kPlanOk ? sig[n - 1] : 1;
+      if (__builtin_mul_overflow(det, sSig[l], &det) || det >= ((int64_t)1 << 62)) st = kPlanTooMany;
+    const int64_t L = st == kPlanOk ? sSig[n - 1] : 1;
     if (st == kPlanOk && L >= ((int64_t)1 << 31)) st = kPlanBigFactor;
-    if (st == kPlanOk) {  // second run: the same operations, V modulo L
-      for (int i = 0; i < n * n; ++i) M[i] = D[i];
-      st = smith64(n, M, V, L, sig);
+    if (st == kPlanOk && L > 1) {  // second run, V modulo L
+      __syncthreads();
+      for (int e = lane; e < n * n; e += 64) sM[e] = D[e];
+      st = smith_wave(n, sM, sV, L, sQ, sSig, lane);
     }
-    if (st == kPlanOk && !solve_complex(n, D, A, br, bi)) st = kPlanSingular;
+    __syncthreads();
+    if (st == kPlanOk && !solve_wave(n, D, sA, sB, sB + kPlanMaxN, sF, lane)) st = kPlanSingular;
     if (st == kPlanOk) {
       int nlive = 0;
-      for (int l = 0; l < n; ++l) nlive += sig[l] > 1;
-      rec[0] = L;
-      rec[1] = nlive;
-      for (int i = 0; i < n; ++i) {
-        rec[2 + 2 * i] = __double_as_longlong(br[i]);
-        rec[3 + 2 * i] = __double_as_longlong(bi[i]);
+      for (int l = 0; l < n; ++l) nlive += sSig[l] > 1;
+      if (lane == 0) {
+        rec[0] = L;
+        rec[1] = nlive;
+      }
+      if (lane < n) {
+        rec[2 + 2 * lane] = __double_as_longlong(sB[lane]);
+        rec[3 + 2 * lane] = __double_as_longlong(sB[kPlanMaxN + lane]);
       }
       int64_t *rs = rec + 2 + 2 * n, *rc = rs + nlive;
-      int q = 0;
+      int qn = 0;
       for (int l = 0; l < n; ++l) {
-        if (sig[l] == 1) continue;
-        rs[q] = sig[l];
-        const int64_t step = L / sig[l];
-        for (int i = 0; i < n; ++i) rc[q * n + i] = (V[i * n + l] % sig[l]) * step % L;
-        ++q;
+        const int64_t sg = sSig[l];
+        if (sg == 1) continue;
+        if (lane == 0) rs[qn] = sg;
+        if (lane < n) rc[qn * n + lane] = ((int64_t)sV[lane * n + l] % sg) * (L / sg) % L;
+        ++qn;
       }
-      det_out[c] = det;
     }
-    status[c] = st;
+    if (lane == 0) {
+      status[c] = st;
+      det_out[c] = st == kPlanOk ? det : 0;
+    }
+    __syncthreads();  // the next cell reuses the LDS arrays
   }
 }
 
@@ -280,15 +343,14 @@ int start_status_code(int32_t st) {
 }
 
 hipError_t launch_start_plan(int n, int64_t num_cells, const int32_t *D, const double *beta,
-                             int64_t *rec, int32_t *status, int64_t *det, int64_t *ws,
-                             int64_t ws_cells, hipStream_t stream) {
+                             int64_t *rec, int32_t *status, int64_t *det, hipStream_t stream) {
+  if (n < 1 || n > kPlanMaxN) return hipErrorInvalidValue;
   prof_begin(stream);
-  for (int64_t c0 = 0; c0 < num_cells; c0 += ws_cells) {
-    const int64_t c1 = c0 + ws_cells < num_cells ? c0 + ws_cells : num_cells;
-    const int64_t blocks = (c1 - c0 + 63) / 64;
-    hipLaunchKernelGGL(k_start_plan, dim3((unsigned)blocks), dim3(64), 0, stream, n, c0, c1, D,
-                       beta, rec, status, det, ws);
-  }
+  int64_t blocks = num_cells;
+  const int64_t cap = (int64_t)num_cus() * 16;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_start_plan, dim3((unsigned)blocks), dim3(64), 0, stream, n, num_cells, D,
+                     beta, rec, status, det);
   prof_end(stream, "k_start_plan");
   return hipGetLastError();
 }
