@@ -284,17 +284,41 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// q = t d + r with 0 <= r < d, returns t, for 0 <= q < 2^62 and 1 <= d < 2^31, inv = 1/d
+// rounded: the FP64 estimate of q/d is within 1537 of it, the remainder it leaves is below 2^42
+// and exact in FP64, whose quotient estimate is within one; a last step fixes that one.  (The
+// compiler's 64-bit division is a long software routine; this is a few instructions.)
+__device__ __forceinline__ int64_t divmod62(int64_t q, int64_t d, double inv, int64_t &r) {
+  int64_t t = (int64_t)((double)q * inv);
+  int64_t e = q - t * d;
+  const int64_t t2 = (int64_t)floor((double)e * inv);
+  t += t2;
+  e -= t2 * d;
+  if (e < 0) {
+    e += d;
+    --t;
+  } else if (e >= d) {
+    e -= d;
+    ++t;
+  }
+  r = e;
+  return t;
+}
+
 // One thread per (root row, coordinate): the cell by binary search over the rows' starts, the
-// root index's mixed-radix digits over the cell's invariant factors above one (first fastest),
-// the fractional part sum_l j_l cm[l][i] mod L, the imaginary part reduced into [-pi, pi).
+// root index's mixed-radix digits over the cell's invariant factors above one (first fastest;
+// the last digit is what remains), the fractional part sum_l j_l cm[l][i] mod L, the imaginary
+// part reduced into [-pi, pi).
 __global__ void __launch_bounds__(256)
     k_binomial_starts(int n, int num_cells, const StartHdr *__restrict__ hdr,
                       const int64_t *__restrict__ rec_all, int64_t rows, double *__restrict__ z) {
   const int64_t total = rows * n;
+  const double inv_n = 1.0 / (double)n;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = g / n;
-    const int i = (int)(g - row * n);
+    int64_t ii;
+    const int64_t row = divmod62(g, n, inv_n, ii);
+    const int i = (int)ii;
     int lo = 0, hi = num_cells - 1;  // last cell with row0 <= row
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -307,15 +331,21 @@ __global__ void __launch_bounds__(256)
     const int nlive = (int)d[1];
     const double zr = __longlong_as_double(d[2 + 2 * i]), zi0 = __longlong_as_double(d[3 + 2 * i]);
     const int64_t *rs = d + 2 + 2 * n, *rc = rs + nlive;
+    const double inv_L = 1.0 / (double)L;
     int64_t q = h.first + (row - h.row0), num = 0;
     for (int l = 0; l < nlive; ++l) {
-      const int64_t sg = rs[l];
-      const int64_t j = q % sg;
-      q /= sg;
-      num = (num + j * rc[(int64_t)l * n + i]) % L;
+      int64_t j = q;
+      if (l + 1 < nlive) {
+        const int64_t sg = rs[l];
+        q = divmod62(q, sg, 1.0 / (double)sg, j);
+      }
+      int64_t t;  // j < sigma_l <= L and the column entry < L: the product is below 2^62
+      divmod62(j * rc[(int64_t)l * n + i], L, inv_L, t);
+      num += t;
+      if (num >= L) num -= L;
     }
     const double two_pi = 6.283185307179586476925286766559;
-    double im = zi0 + two_pi * ((double)num / (double)L) + 3.14159265358979323846264338327950;
+    double im = zi0 + two_pi * ((double)num * inv_L) + 3.14159265358979323846264338327950;
     im -= two_pi * floor(im / two_pi);
     im -= 3.14159265358979323846264338327950;
     if (im >= 3.14159265358979323846264338327950) im -= two_pi;  // rounding at the top edge
