@@ -24,17 +24,21 @@
 
 namespace hom {
 
-constexpr int kProjBlock = 128;
+// Four waves per block up to 16-lane groups (the tables are shared by more waves); two for 32.
+template <int N>
+__host__ __device__ constexpr int proj_block() {
+  return N <= 16 ? 256 : 128;
+}
 
 // Columns kept per row: the n + 1 unknowns and the s and H columns (the padding unknowns' columns
 // are zero in every real row), compressed as k <= n -> column k, k = n+1 -> column N (d/ds),
 // k = n+2 -> column N+1 (H).
 template <int N>
-__host__ __device__ constexpr size_t proj_group_bytes() {
-  return (size_t)N * 16                /* z_j, then 1/y_j (two passes over the same slots) */
-         + (size_t)N * 16              /* y_j */
-         + (size_t)(N - 2) * N * 16    /* reflectors W[i][k], i <= n <= N-3, k <= n+2 < N */
-         + (size_t)N * 8;              /* beta_i */
+__host__ __device__ constexpr size_t proj_group_bytes(int n) {
+  return (size_t)N * 16                        /* z_j, then 1/y_j (two passes over the same slots) */
+         + (size_t)N * 16                      /* y_j */
+         + (size_t)(n + 1) * (n + 3) * 16      /* reflectors W[i][k], i <= n, k <= n + 2 */
+         + ((size_t)(n + 2) * 8 + 15) / 16 * 16;  /* beta_i, then |L_ii|; 16-byte multiple */
 }
 
 // sum over an aligned group of N lanes (N a power of two): a butterfly of xor shuffles
@@ -50,8 +54,10 @@ __device__ __forceinline__ double group_sum(double v) {
 
 __device__ __forceinline__ Cx<double> cconj(Cx<double> a) { return {a.x, -a.y}; }
 
+// Up to 16-lane groups the registers are bounded for two waves per SIMD (a few spill; measured
+// faster than one wave without spills).
 template <int N, bool GT>
-__global__ void __launch_bounds__(kProjBlock)
+__global__ void __launch_bounds__(proj_block<N>()) __attribute__((amdgpu_waves_per_eu(N <= 16 ? 2 : 1)))
     k_step_proj(SysDev sd, const double *__restrict__ c, int64_t P, const double *__restrict__ y,
                 const double *__restrict__ s, double *__restrict__ dE, double *__restrict__ dN,
                 int32_t *__restrict__ status, size_t table_bytes) {
@@ -61,12 +67,13 @@ __global__ void __launch_bounds__(kProjBlock)
   const Geo<N> geo;
   const int n = sd.n, nu = n + 1, r = geo.r;
   char *gb = smem + table_bytes +
-             ((threadIdx.x >> 6) * Geo<N>::G + (geo.valid ? geo.g : 0)) * proj_group_bytes<N>();
+             ((threadIdx.x >> 6) * Geo<N>::G + (geo.valid ? geo.g : 0)) * proj_group_bytes<N>(n);
   Cx<double> *sZ = reinterpret_cast<Cx<double> *>(gb);
   Cx<double> *sY = sZ + N;
-  Cx<double> *sW = sY + N;  // [N - 2][N]
-  double *sB = reinterpret_cast<double *>(sW + (N - 2) * N);
-  const int64_t gpb = (kProjBlock / 64) * Geo<N>::G;
+  const int ldw = n + 3;     // compressed columns of a reflector
+  Cx<double> *sW = sY + N;  // [n + 1][n + 3]
+  double *sB = reinterpret_cast<double *>(sW + (n + 1) * ldw);
+  const int64_t gpb = (proj_block<N>() / 64) * Geo<N>::G;
   const int64_t stride = (int64_t)gridDim.x * gpb;
   const int64_t p0 = (int64_t)blockIdx.x * gpb + (threadIdx.x >> 6) * Geo<N>::G + geo.g;
   // this lane's compressed column: k <= n unknowns, n+1 the s column, n+2 the H column
@@ -122,16 +129,20 @@ __global__ void __launch_bounds__(kProjBlock)
       if (r == i && geo.valid) {
         double nrm2 = 0.0;
 #pragma unroll
-        for (int col = i; col < N + 2; ++col) nrm2 += row[col].x * row[col].x + row[col].y * row[col].y;
+        for (int col = 0; col < N + 2; ++col)
+          if (col >= i) nrm2 += row[col].x * row[col].x + row[col].y * row[col].y;
         const double nx = sqrt(nrm2);
-        const Cx<double> x0 = row[i];
+        Cx<double> x0 = {0.0, 0.0};  // row[i] by selects: i may stay a loop counter, and a
+#pragma unroll                        // runtime index would move the row to scratch memory
+        for (int col = 0; col < N - 2; ++col)
+          if (col == i) x0 = row[col];
         const double a0 = sqrt(x0.x * x0.x + x0.y * x0.y);
         const Cx<double> alpha = a0 > 0.0 ? Cx<double>{-x0.x / a0 * nx, -x0.y / a0 * nx}
                                           : Cx<double>{-nx, 0.0};
         const Cx<double> v0 = {x0.x - alpha.x, x0.y - alpha.y};
         const double wn2 = v0.x * v0.x + v0.y * v0.y + (nrm2 - a0 * a0);
         // compressed storage of w: k <= n, then the s and H columns
-        Cx<double> *W = sW + i * N;
+        Cx<double> *W = sW + i * ldw;
 #pragma unroll
         for (int col = 0; col < N + 2; ++col) {
           if (col < i) continue;
@@ -140,16 +151,16 @@ __global__ void __launch_bounds__(kProjBlock)
           W[k] = col == i ? cconj(v0) : cconj(row[col]);
         }
         sB[i] = wn2 > 0.0 ? 2.0 / wn2 : 0.0;
-        sB[N - 1] = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);  // |L_ii|, read below
+        sB[nu] = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);  // |L_ii|, read below
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __builtin_amdgcn_wave_barrier();
       const double beta = geo.valid ? sB[i] : 0.0;
-      const double lii = geo.valid ? sB[N - 1] : 0.0;
+      const double lii = geo.valid ? sB[nu] : 0.0;
       lmin = fmin(lmin, lii);
       lmax = fmax(lmax, lii);
       if (r > i) {  // rows below apply it: row -= beta (row . w) w^H
-        const Cx<double> *W = sW + i * N;
+        const Cx<double> *W = sW + i * ldw;
         Cx<double> dot = {0.0, 0.0};
 #pragma unroll
         for (int col = 0; col < N + 2; ++col) {
@@ -176,7 +187,7 @@ __global__ void __launch_bounds__(kProjBlock)
     for (int i = N - 3; i >= 0; --i) {
       if (i > n) continue;  // uniform
       const bool mine = geo.valid && kcol <= nu + 1 && (kcol >= i || kcol > n);
-      const Cx<double> wk = mine ? sW[i * N + kcol] : Cx<double>{0.0, 0.0};
+      const Cx<double> wk = mine ? sW[i * ldw + kcol] : Cx<double>{0.0, 0.0};
       const double beta = geo.valid ? sB[i] : 0.0;
       // d = w^H x over the group
       const Cx<double> t1 = cmul(cconj(wk), x1), t2 = cmul(cconj(wk), x2);
@@ -219,8 +230,9 @@ static hipError_t step_proj_n(const System &S, const void *cws, const double *c,
                               const double *y, const double *s, double *dE, double *dN,
                               int32_t *status, hipStream_t stream) {
   const size_t tb = (S.lds_bytes + 15) & ~(size_t)15;
-  const size_t lds = tb + (size_t)(kProjBlock / 64) * Geo<N>::G * proj_group_bytes<N>();
-  const int64_t gpb = (kProjBlock / 64) * Geo<N>::G;
+  constexpr int block = proj_block<N>();
+  const size_t lds = tb + (size_t)(block / 64) * Geo<N>::G * proj_group_bytes<N>(S.n);
+  const int64_t gpb = (block / 64) * Geo<N>::G;
   const int64_t need = (P + gpb - 1) / gpb;
   const int64_t cap = (int64_t)num_cus() * 16;
   const unsigned grid = (unsigned)(need < cap ? (need > 0 ? need : 1) : cap);
@@ -228,7 +240,7 @@ static hipError_t step_proj_n(const System &S, const void *cws, const double *c,
   char label[64];
   snprintf(label, sizeof label, "k_step_proj<%d>", N);
   prof_begin(stream);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kProjBlock), lds, stream, S.dev(cws), c, P, y, s, dE,
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, stream, S.dev(cws), c, P, y, s, dE,
                      dN, status, tb);
   prof_end(stream, label);
   return hipGetLastError();
