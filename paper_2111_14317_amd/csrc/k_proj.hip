@@ -41,15 +41,28 @@ __host__ __device__ constexpr size_t proj_group_bytes(int n) {
          + ((size_t)(n + 2) * 8 + 15) / 16 * 16;  /* beta_i, then |L_ii|; 16-byte multiple */
 }
 
-// sum over an aligned group of N lanes (N a power of two): a butterfly of xor shuffles
+// v from another lane of the same row of 16 by a DPP pattern (two 32-bit moves, no LDS)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// sum over an aligned group of N lanes (N a power of two), the same value in every lane: pairs
+// within quads (lane ^ 1, lane ^ 2), then quads mirrored within 8 lanes, then halves mirrored
+// within 16 (DPP), then the two rows of 16 of a 32-lane group (a shuffle).  Each step adds two
+// partial sums that are equal in both lanes of a pair, so every lane rounds identically.
 template <int N>
 __device__ __forceinline__ double group_sum(double v) {
-  if constexpr (N > 1) {
-    v += __shfl_xor(v, N / 2, 64);
-    return group_sum<N / 2>(v);
-  } else {
-    return v;
-  }
+  if constexpr (N >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (N >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (N >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if constexpr (N >= 16) v += dpp_f64<0x140>(v); // row_mirror
+  if constexpr (N >= 32) v += __shfl_xor(v, 16, 64);
+  static_assert(N <= 32, "groups of at most 32 lanes");
+  return v;
 }
 
 __device__ __forceinline__ Cx<double> cconj(Cx<double> a) { return {a.x, -a.y}; }
@@ -127,10 +140,15 @@ __global__ void __launch_bounds__(proj_block<N>()) __attribute__((amdgpu_waves_p
       if (i > n) break;  // uniform
       // lane i: the reflector of its entries in columns i.. (w = conj(x) - conj(alpha) e_i)
       if (r == i && geo.valid) {
-        double nrm2 = 0.0;
+        double nrm2a = 0.0, nrm2b = 0.0;  // two partial sums: half the dependent chain
 #pragma unroll
-        for (int col = 0; col < N + 2; ++col)
-          if (col >= i) nrm2 += row[col].x * row[col].x + row[col].y * row[col].y;
+        for (int col = 0; col < N + 2; ++col) {
+          if (col < i) continue;
+          const double t = row[col].x * row[col].x + row[col].y * row[col].y;
+          if (col & 1) nrm2b += t;
+          else nrm2a += t;
+        }
+        const double nrm2 = nrm2a + nrm2b;
         const double nx = sqrt(nrm2);
         Cx<double> x0 = {0.0, 0.0};  // row[i] by selects: i may stay a loop counter, and a
 #pragma unroll                        // runtime index would move the row to scratch memory
@@ -161,15 +179,16 @@ __global__ void __launch_bounds__(proj_block<N>()) __attribute__((amdgpu_waves_p
       lmax = fmax(lmax, lii);
       if (r > i) {  // rows below apply it: row -= beta (row . w) w^H
         const Cx<double> *W = sW + i * ldw;
-        Cx<double> dot = {0.0, 0.0};
+        Cx<double> da = {0.0, 0.0}, db = {0.0, 0.0};  // two partial sums
 #pragma unroll
         for (int col = 0; col < N + 2; ++col) {
           if (col < i || (col < N && col > n)) continue;
           const int k = col < N ? col : nu + (col - N);
           const Cx<double> wk = geo.valid ? W[k] : Cx<double>{0.0, 0.0};
-          dot = cfma(dot, row[col], wk);
+          if (col & 1) db = cfma(db, row[col], wk);
+          else da = cfma(da, row[col], wk);
         }
-        const Cx<double> f = {beta * dot.x, beta * dot.y};
+        const Cx<double> f = {beta * (da.x + db.x), beta * (da.y + db.y)};
 #pragma unroll
         for (int col = 0; col < N + 2; ++col) {
           if (col < i || (col < N && col > n)) continue;
