@@ -141,8 +141,11 @@ __global__ void __launch_bounds__(kBlock)
 
 // Evaluation + consolidated solve.  The loop over points is wave-uniform (the LU shuffles);
 // groups past the end compute on a dummy point and store nothing.
+// The mixed form up to 12 lanes per group: three waves per SIMD (some registers spill; 2-5%
+// faster at 1M points than two waves without spills).  The FP64 form measured the same at three.
 template <int N, bool MIXED, bool GT>
-__global__ void __launch_bounds__(kBlock) k_step(SysDev sd, const double *__restrict__ c,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MIXED && N <= 12 ? 3 : 1)))
+    k_step(SysDev sd, const double *__restrict__ c,
                                                  int64_t P, const double *__restrict__ z,
                                                  const double *__restrict__ s,
                                                  double *__restrict__ dE,
