@@ -151,7 +151,7 @@ def test_full_size_cell_properties(hom):
 def test_plan_counts_and_errors(hom):
     """The GPU plan's root counts equal |det D| (numpy) and the oracle's; singular D, zero beta,
     a range outside a cell's roots and too few output rows are refused (HOM_EINVAL); a largest
-    invariant factor beyond 2^31 is HOM_EUNSUPPORTED."""
+    invariant factor beyond 2^31 and a Smith form beyond int64 are HOM_EUNSUPPORTED."""
     import ctypes
     import torch
     lib = hom.lib
@@ -186,3 +186,10 @@ def test_plan_counts_and_errors(hom):
     big = np.array([[[65536, 0], [0, 32769]]], np.int32)  # invariant factors 1, 65536 * 32769
     assert lib.hom_binomial_starts(2, 1, P(big), P(beta), None, None, P(num), None, 0,
                                    None) == hom.HOM_EUNSUPPORTED
+    # entries near 2^31: the elimination's products leave int64 before the factors are known
+    ovf = np.array([[[-806518787, 643041142, 2119013548], [1405629503, 160003470, -1861309367],
+                     [2123086262, -1491957382, -1356837216]]], np.int32)
+    b3 = np.ones((1, 3), np.complex128)
+    assert lib.hom_binomial_starts(3, 1, P(ovf), P(b3), None, None, P(num), None, 0,
+                                   None) == hom.HOM_EUNSUPPORTED
+    assert b"int64" in lib.hom_last_error()
