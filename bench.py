@@ -693,6 +693,55 @@ def run_step_proj(hom, torch, P=65536, reps=5):
     return rec
 
 
+# the paper's own timings (Tables 1-2): wall seconds for 100 consecutive consolidated Euler-Newton
+# steps in FP64 by number of points, V100 column (another machine: context only)
+PAPER_V100_S = {"ps14": {10: 0.0222, 50: 0.0274, 250: 0.0296, 500: 0.0313, 1000: 0.0355},
+                "ps24": {250: 0.0728, 500: 0.0757, 1000: 0.0852}}
+
+
+def run_paper_shapes(hom, torch, steps=100):
+    """100 consecutive consolidated steps (one hom_step, then z <- z + ds dE + dN, s <- s + ds) in
+    FP64 on systems of the sizes of the paper's timing systems (n = 14 with 184 monomials, n = 24
+    with 324; random, not the systems) at the paper's point counts: wall seconds on the host clock
+    around the 100 steps (as the paper times them, launches included) and point-steps/s, beside
+    the paper's V100 figures."""
+    import numpy as np
+
+    import workloads as W
+    out = {}
+    for name in ("ps14", "ps24"):
+        sys_, z, s = W.config_system(name, P=1000)
+        h = hom.System.from_workload(sys_)
+        c = torch.tensor(sys_.c, dtype=torch.complex128, device="cuda")
+        rec = {}
+        for P in (10, 50, 250, 500, 1000):
+            z0 = torch.tensor(z[:P], dtype=torch.complex128, device="cuda")
+            s0 = torch.tensor(s[:P], dtype=torch.float64, device="cuda")
+            ds = 1e-3
+
+            def run(k):
+                zt, st = z0, s0
+                for _ in range(k):
+                    dE, dN, _ = hom.step(h, c, zt, st)
+                    zt = zt + ds * dE + dN
+                    st = st + ds
+                return zt
+
+            run(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run(steps)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) * 100 / steps
+            rec[str(P)] = {"s_per_100_steps": sec, "point_steps_per_s": P * 100 / sec,
+                           "paper_v100_s_per_100_steps": PAPER_V100_S[name].get(P)}
+        out[name] = {"n": sys_.n, "monomials": int(np.sum(sys_.m)), "by_points": rec}
+        print(f"# paper shape {name} (n={sys_.n}, M={int(np.sum(sys_.m))}), s per 100 steps by P: "
+              + ", ".join(f"{k}: {v['s_per_100_steps']:.4f} (V100 {v['paper_v100_s_per_100_steps']})"
+                          for k, v in rec.items()), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -831,6 +880,7 @@ def main():
         out["common_support_n32_m128"] = run_union(hom, torch, args.dense_points)
         out["start_points_n10_cell"] = run_starts(hom, torch)
         out["step_proj_n10_65536_points"] = run_step_proj(hom, torch)
+        out["paper_shapes_100_steps_fp64"] = run_paper_shapes(hom, torch)
     # the units' rates measured on this device (the published peaks stay the roofline denominators)
     peaks = hom.peak_probes()
     out["measured_peaks"] = peaks

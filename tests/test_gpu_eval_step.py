@@ -28,9 +28,11 @@ def _uneven_system(seed=3, n=5):
 
 
 CASES = [("c1", 4096), ("c2", 8191), ("c5", 3001)]
+# FP64 forms also at the sizes of the paper's own timing systems (n = 14 and 24, 0/1 exponents)
+CASES_FP64 = CASES + [("ps14", 1000), ("ps24", 1000)]
 
 
-@pytest.mark.parametrize("cfg,P", CASES)
+@pytest.mark.parametrize("cfg,P", CASES_FP64)
 def test_eval_fp64(hom, cfg, P):
     say(f"[eval fp64] {cfg} P={P}")
     sys, z, s = W.config_system(cfg, P=P)
@@ -116,7 +118,7 @@ def _dir_err(a, b):
     return np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-300)
 
 
-@pytest.mark.parametrize("cfg,P", CASES)
+@pytest.mark.parametrize("cfg,P", CASES_FP64)
 def test_step_fp64(hom, cfg, P):
     say(f"[step fp64] {cfg} P={P}")
     sys, z, s = W.config_system(cfg, P=P)

@@ -151,8 +151,13 @@ CONFIGS = {
     "c2": dict(n=10, m=12, exps=("u", -3, 3), coef="unit", lift=63, P=65536),
     "c3": dict(n=32, m=128, exps=("z", 4, 0.3), coef="gauss", lift=255, P=262144),
     "c5": dict(n=8, m=16, exps=("u", -2, 2), coef="unit", lift=31, P=16384),
+    # the sizes of the paper's timing systems (Tables 1-2: n = 14 with 184 monomials, n = 24 with
+    # 324), not the systems: monomials split as evenly as possible over the equations, 0/1
+    # exponents (each entry 1 with probability 0.3), up to 1000 points
+    "ps14": dict(n=14, m=[14] * 2 + [13] * 12, exps=("b", 0.3), coef="unit", lift=31, P=1000),
+    "ps24": dict(n=24, m=[14] * 12 + [13] * 12, exps=("b", 0.3), coef="unit", lift=31, P=1000),
 }
-CONFIG_INDEX = {"c1": 0, "c2": 1, "c3": 2, "c4": 3, "c5": 4}
+CONFIG_INDEX = {"c1": 0, "c2": 1, "c3": 2, "c4": 3, "c5": 4, "ps14": 5, "ps24": 6}
 
 
 def streams(cfg: str):
@@ -165,11 +170,14 @@ def _draw_for(spec):
     kind = spec[0]
     if kind == "u":
         return _uniform_exps(spec[1], spec[2])
+    if kind == "b":  # 0/1 entries, 1 with probability spec[1]
+        return lambda rng, n: (rng.random(n) < spec[1]).astype(np.int64)
     return _sparse_exps(spec[1], spec[2])
 
 
 def config_system(cfg: str, P: int | None = None):
-    """System and random evaluation points of configuration `cfg` ('c1', 'c2', 'c3', 'c5')."""
+    """System and random evaluation points of configuration `cfg` ('c1', 'c2', 'c3', 'c5', 'ps14',
+    'ps24')."""
     spec = CONFIGS[cfg]
     r_sup, r_coef, r_lift, r_pts, _, _ = streams(cfg)
     sys = random_system(spec["n"], spec["m"], _draw_for(spec["exps"]), spec["coef"], spec["lift"],
