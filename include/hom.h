@@ -315,7 +315,7 @@ int hom_endpoint_grad(hom_system_t sys, const double *c, int64_t P, const double
  *   num_roots  host int64 [num_cells], out: |det D_c|, the number of roots of cell c.
  *   z      device complex [z_rows][n] or NULL: the roots, cell after cell; Im z in [-pi, pi).
  *          NULL: only num_roots is computed.
- * The cells are planned on the GPU, one thread per cell (the Smith form on int64 with overflow
+ * The cells are planned on the GPU, one wavefront per cell (the Smith form on int64 with overflow
  * checks, twice; z_base by an FP64 LU solve), then one launch writes the roots.  n in [1, 32];
  * the Smith form's entries within int64, |det D_c| < 2^62 and its largest invariant factor
  * < 2^31 (HOM_EUNSUPPORTED otherwise).  Blocks until the plans are read back (each cell's status
