@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(proj_block<N>()) __attribute__((amdgpu_waves_p
     double lmin = INFINITY, lmax = 0.0;
 #pragma unroll
     for (int i = 0; i < N - 2; ++i) {
-      if (i > n) break;  // uniform
+      if (i > n) continue;  // uniform (a static trip count lets the loop unroll)
       // lane i: the reflector of its entries in columns i.. (w = conj(x) - conj(alpha) e_i)
       if (r == i && geo.valid) {
         double nrm2a = 0.0, nrm2b = 0.0;  // two partial sums: half the dependent chain
