@@ -66,7 +66,7 @@ void prof_begin(hipStream_t stream) {
   g_open_units = nullptr;
   if (!g_prof || g_recs.size() >= kMaxRecs) return;
   g_open = pool_get();
-  if (g_open) hipEventRecord(g_open, stream);
+  if (g_open) (void)hipEventRecord(g_open, stream);
 }
 
 __global__ void k_prof_zero(unsigned long long *p) { *p = 0ull; }
@@ -83,7 +83,7 @@ void prof_end(hipStream_t stream, const char *label) {
   if (!g_prof || !g_open) return;
   hipEvent_t b = pool_get();
   if (!b) return;
-  hipEventRecord(b, stream);
+  (void)hipEventRecord(b, stream);
   ProfRec r;
   r.a = g_open;
   r.b = b;
@@ -250,14 +250,14 @@ static void build_dense(int n, const int32_t *m, const int8_t *A, const double *
 }
 
 static void free_system(System &S) {
-  hipFree(S.dT);
-  hipFree(S.dmk);
-  hipFree(S.doff);
-  hipFree(S.dA);
-  hipFree(S.dBatch);
-  hipFree(S.dT_all);
-  hipFree(S.dInts_all);
-  hipFree(S.dDense);
+  (void)hipFree(S.dT);
+  (void)hipFree(S.dmk);
+  (void)hipFree(S.doff);
+  (void)hipFree(S.dA);
+  (void)hipFree(S.dBatch);
+  (void)hipFree(S.dT_all);
+  (void)hipFree(S.dInts_all);
+  (void)hipFree(S.dDense);
 }
 
 // This call's table-order coefficients for a system whose tables stay in global memory (a
@@ -610,7 +610,7 @@ int hom_create_batch(int num_sys, const hom_sys_desc *descs, int flags, hom_syst
 int hom_destroy(hom_system_t h) {
   g_err.clear();
   if (!h) return HOM_OK;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   free_system(h->s);
   delete h;
   return HOM_OK;
@@ -900,8 +900,8 @@ int hom_track(hom_system_t h, const double *c, int64_t P, double *z, double *s, 
   } else if (e == hipSuccess && mixed) {
     e = launch_track(h->s, cws, c, P, z, s, ds, status, counters, pr64, false, queue, st);
   }
-  if (fork) hipEventDestroy(fork);
-  if (join) hipEventDestroy(join);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
   hipError_t e2 = coeff_end(cws, st);
   hipError_t e3 = hipFreeAsync(queue, st);
   HOM_HIP(e, "hom_track");

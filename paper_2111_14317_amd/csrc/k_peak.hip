@@ -135,7 +135,7 @@ hipError_t time_launches(hipStream_t st, int reps, F launch, double *ms) {
   if (e != hipSuccess) return e;
   e = hipEventCreate(&e1);
   if (e != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return e;
   }
   launch();
@@ -149,8 +149,8 @@ hipError_t time_launches(hipStream_t st, int reps, F launch, double *ms) {
   float t = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
   *ms = (double)t / reps;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return e;
 }
 
@@ -183,8 +183,8 @@ hipError_t peak_probe(int kind, double *rate, hipStream_t st) {
       if (e == hipSuccess) *rate = (double)bytes / (ms * 1e-3) / 1e9;  // GB/s
     }
     hipError_t e2 = hipStreamSynchronize(st);
-    if (buf) hipFree(buf);
-    if (out) hipFree(out);
+    if (buf) (void)hipFree(buf);
+    if (out) (void)hipFree(out);
     return e != hipSuccess ? e : e2;
   }
   void *out = nullptr;
@@ -250,7 +250,7 @@ hipError_t peak_probe(int kind, double *rate, hipStream_t st) {
   }
   if (e == hipSuccess) *rate = work / (ms * 1e-3) / unit;
   hipError_t e2 = hipStreamSynchronize(st);
-  hipFree(out);
+  (void)hipFree(out);
   return e != hipSuccess ? e : e2;
 }
 
