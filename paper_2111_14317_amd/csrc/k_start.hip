@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "hom_internal.h"
+#include "hom_intdiv.h"
 
 namespace hom {
 
@@ -282,27 +283,6 @@ __global__ void __launch_bounds__(64)
     }
     __syncthreads();  // the next cell reuses the LDS arrays
   }
-}
-
-// q = t d + r with 0 <= r < d, returns t, for 0 <= q < 2^62 and 1 <= d < 2^31, inv = 1/d
-// rounded: the FP64 estimate of q/d is within 1537 of it, the remainder it leaves is below 2^42
-// and exact in FP64, whose quotient estimate is within one; a last step fixes that one.  (The
-// compiler's 64-bit division is a long software routine; this is a few instructions.)
-__device__ __forceinline__ int64_t divmod62(int64_t q, int64_t d, double inv, int64_t &r) {
-  int64_t t = (int64_t)((double)q * inv);
-  int64_t e = q - t * d;
-  const int64_t t2 = (int64_t)floor((double)e * inv);
-  t += t2;
-  e -= t2 * d;
-  if (e < 0) {
-    e += d;
-    --t;
-  } else if (e >= d) {
-    e -= d;
-    ++t;
-  }
-  r = e;
-  return t;
 }
 
 // One thread per (root row, coordinate): the cell by binary search over the rows' starts, the
