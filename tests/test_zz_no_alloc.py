@@ -56,6 +56,27 @@ def test_noalloc_equals_track(hom, which, prec):
         assert ok.mean() >= 0.9
 
 
+@pytest.mark.parametrize("prec,pred", [("mixed", "rk4"), ("fp64", "hermite")])
+def test_noalloc_predictors(hom, prec, pred):
+    """The same with the Runge-Kutta (mixed form) and cubic Hermite (FP64 form) predictors."""
+    import torch
+    csys, cell, z0 = W.planted_config("c5", P=512)
+    say(f"[noalloc] {prec} {pred} n={csys.n}")
+    precision = hom.FP64 if prec == "fp64" else hom.MIXED
+    predictor = hom.PREDICT_RK4 if pred == "rk4" else hom.PREDICT_HERMITE
+    h = hom.System.from_workload(csys)
+    c = torch.tensor(csys.c, dtype=torch.complex128, device="cuda")
+    for P in (512, 130):
+        ref = hom.track(h, c, z0[:P], -32.0, hom.default_params(
+            precision, flags=hom.TRACK_SERIAL, predictor=predictor))
+        got = hom.track_noalloc(h, c, hom.new_state(z0[:P], -32.0),
+                                hom.default_params(precision, predictor=predictor))
+        torch.cuda.synchronize()
+        for f in ("z", "s", "ds", "status", "counters"):
+            assert np.array_equal(_np(getattr(got, f)), _np(getattr(ref, f))), (P, f)
+        assert (_np(got.status) == 0).mean() >= 0.9
+
+
 def test_noalloc_rejects_what_it_cannot_hold(hom):
     """A coefficient table beyond the scratch (one equation with 6000 monomials at n = 32) and a
     batch handle are refused with a clear error before any launch."""
