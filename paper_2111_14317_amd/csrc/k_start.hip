@@ -285,52 +285,114 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// One thread per (root row, coordinate): the cell by binary search over the rows' starts, the
-// root index's mixed-radix digits over the cell's invariant factors above one (first fastest;
-// the last digit is what remains), the fractional part sum_l j_l cm[l][i] mod L, the imaginary
-// part reduced into [-pi, pi).
-__global__ void __launch_bounds__(256)
+// One thread per root row, 64 rows per block (one wave) per tile, grid-stride over tiles: the
+// cell by binary search over the rows' starts (skipped while the row stays in the previous row's
+// cell), the root index's mixed-radix digits over the cell's invariant factors above one (first
+// fastest; the last digit is what remains), each coordinate's fractional part
+// num_i = sum_l j_l cm[l][i] mod L, the imaginary part reduced into [-pi, pi).  In a cell with one
+// factor above one (j = the root index itself), the next row of a thread is gridDim * 64 roots
+// further, so num_i grows by a fixed increment mod L: one addition per coordinate instead of a
+// product.  The rows go through LDS and leave in contiguous 16-byte pieces.  KN >= n.
+constexpr int kStartTile = 64;
+template <int KN>
+__global__ void __launch_bounds__(kStartTile)
     k_binomial_starts(int n, int num_cells, const StartHdr *__restrict__ hdr,
                       const int64_t *__restrict__ rec_all, int64_t rows, double *__restrict__ z) {
-  const int64_t total = rows * n;
-  const double inv_n = 1.0 / (double)n;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int64_t ii;
-    const int64_t row = divmod62(g, n, inv_n, ii);
-    const int i = (int)ii;
-    int lo = 0, hi = num_cells - 1;  // last cell with row0 <= row
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (hdr[mid].row0 <= row) lo = mid;
-      else hi = mid - 1;
-    }
-    const StartHdr h = hdr[lo];
-    const int64_t *d = rec_all + (int64_t)lo * start_record_words(n);
-    const int64_t L = d[0];
-    const int nlive = (int)d[1];
-    const double zr = __longlong_as_double(d[2 + 2 * i]), zi0 = __longlong_as_double(d[3 + 2 * i]);
-    const int64_t *rs = d + 2 + 2 * n, *rc = rs + nlive;
-    const double inv_L = 1.0 / (double)L;
-    int64_t q = h.first + (row - h.row0), num = 0;
-    for (int l = 0; l < nlive; ++l) {
-      int64_t j = q;
-      if (l + 1 < nlive) {
-        const int64_t sg = rs[l];
-        q = divmod62(q, sg, 1.0 / (double)sg, j);
+  __shared__ double2 stage[kStartTile * KN];
+  const int t = threadIdx.x;
+  const int64_t tiles = (rows + kStartTile - 1) / kStartTile;
+  const int64_t stride = (int64_t)gridDim.x * kStartTile;  // rows between a thread's rows
+  const double two_pi = 6.283185307179586476925286766559;
+  const double pi = 3.14159265358979323846264338327950;
+  int cur = -1;         // cell of this thread's previous row
+  int64_t prev_q = -1;  // its root index
+  int64_t num[KN], inc[KN];
+#pragma unroll
+  for (int i = 0; i < KN; ++i) num[i] = inc[i] = 0;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t row = tile * kStartTile + t;
+    if (row < rows) {
+      int lo;
+      if (cur >= 0 && row >= hdr[cur].row0 && (cur + 1 == num_cells || row < hdr[cur + 1].row0)) {
+        lo = cur;
+      } else {  // last cell with row0 <= row
+        int a = 0, b2 = num_cells - 1;
+        while (a < b2) {
+          const int mid = (a + b2 + 1) >> 1;
+          if (hdr[mid].row0 <= row) a = mid;
+          else b2 = mid - 1;
+        }
+        lo = a;
       }
-      int64_t t;  // j < sigma_l <= L and the column entry < L: the product is below 2^62
-      divmod62(j * rc[(int64_t)l * n + i], L, inv_L, t);
-      num += t;
-      if (num >= L) num -= L;
+      const StartHdr h = hdr[lo];
+      const int64_t *d = rec_all + (int64_t)lo * start_record_words(n);
+      const int64_t L = d[0];
+      const int nlive = (int)d[1];
+      const int64_t *rs = d + 2 + 2 * n, *rc = rs + nlive;
+      const double inv_L = 1.0 / (double)L;
+      const int64_t q = h.first + (row - h.row0);
+      if (nlive == 1 && lo == cur && q - prev_q == stride) {  // the increment, mod L
+#pragma unroll
+        for (int i = 0; i < KN; ++i) {
+          if (i < n) {
+            num[i] += inc[i];
+            if (num[i] >= L) num[i] -= L;
+          }
+        }
+      } else if (nlive == 1) {  // j = q < L; the products and, for the next rows, the increments
+        int64_t sL;
+        divmod62(stride, L, inv_L, sL);
+#pragma unroll
+        for (int i = 0; i < KN; ++i) {
+          if (i < n) {
+            int64_t tq;  // q and the column entry are below L < 2^31: the products below 2^62
+            divmod62(q * rc[i], L, inv_L, tq);
+            num[i] = tq;
+            divmod62(sL * rc[i], L, inv_L, tq);
+            inc[i] = tq;
+          }
+        }
+      } else {  // several factors: every digit, every product
+#pragma unroll
+        for (int i = 0; i < KN; ++i) {
+          if (i < n) {
+            int64_t qq = q, acc = 0;
+            for (int l = 0; l < nlive; ++l) {
+              int64_t j = qq;
+              if (l + 1 < nlive) {
+                const int64_t sg = rs[l];
+                qq = divmod62(qq, sg, 1.0 / (double)sg, j);
+              }
+              int64_t tq;  // j < sigma_l <= L and the column entry < L: below 2^62
+              divmod62(j * rc[(int64_t)l * n + i], L, inv_L, tq);
+              acc += tq;
+              if (acc >= L) acc -= L;
+            }
+            num[i] = acc;
+          }
+        }
+      }
+      cur = lo;
+      prev_q = q;
+#pragma unroll
+      for (int i = 0; i < KN; ++i) {
+        if (i < n) {
+          const double zr = __longlong_as_double(d[2 + 2 * i]);
+          const double zi0 = __longlong_as_double(d[3 + 2 * i]);
+          double im = zi0 + two_pi * ((double)num[i] * inv_L) + pi;
+          im -= two_pi * floor(im / two_pi);
+          im -= pi;
+          if (im >= pi) im -= two_pi;  // rounding at the top edge
+          stage[t * n + i] = double2{zr, im};
+        }
+      }
     }
-    const double two_pi = 6.283185307179586476925286766559;
-    double im = zi0 + two_pi * ((double)num * inv_L) + 3.14159265358979323846264338327950;
-    im -= two_pi * floor(im / two_pi);
-    im -= 3.14159265358979323846264338327950;
-    if (im >= 3.14159265358979323846264338327950) im -= two_pi;  // rounding at the top edge
-    z[2 * g] = zr;
-    z[2 * g + 1] = im;
+    __syncthreads();
+    const int64_t r0 = tile * kStartTile;
+    const int nrow = rows - r0 < kStartTile ? (int)(rows - r0) : kStartTile;
+    double2 *out = reinterpret_cast<double2 *>(z) + r0 * n;
+    for (int k = t; k < nrow * n; k += kStartTile) out[k] = stage[k];
+    __syncthreads();  // the stage is read before the next tile writes it
   }
 }
 
@@ -368,13 +430,18 @@ hipError_t launch_start_plan(int n, int64_t num_cells, const int32_t *D, const d
 hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *rec,
                                   int64_t rows, double *z, hipStream_t stream) {
   prof_begin(stream);
-  const int64_t total = rows * n;
-  int64_t blocks = (total + 255) / 256;
+  const int64_t tiles = (rows + kStartTile - 1) / kStartTile;
+  int64_t blocks = tiles;
   const int64_t cap = (int64_t)num_cus() * 16;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_binomial_starts, dim3((unsigned)blocks), dim3(256), 0, stream, n,
-                     num_cells, hdr, rec, rows, z);
+  const dim3 grid((unsigned)blocks), block(kStartTile);
+  if (n <= 8)
+    hipLaunchKernelGGL(k_binomial_starts<8>, grid, block, 0, stream, n, num_cells, hdr, rec, rows, z);
+  else if (n <= 16)
+    hipLaunchKernelGGL(k_binomial_starts<16>, grid, block, 0, stream, n, num_cells, hdr, rec, rows, z);
+  else
+    hipLaunchKernelGGL(k_binomial_starts<32>, grid, block, 0, stream, n, num_cells, hdr, rec, rows, z);
   prof_end(stream, "k_binomial_starts");
   return hipGetLastError();
 }
