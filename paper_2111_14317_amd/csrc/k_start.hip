@@ -12,8 +12,8 @@
 // on int64 with overflow checks, the lanes splitting each row and column operation, run twice
 // (the second run repeats the first one's operations and carries V modulo the L the first run
 // found), and z_base by an FP64 LU solve; it writes the cell's record.
-// k_binomial_starts, one thread per (root, coordinate): the root from its record, writing
-// consecutive doubles, so the launch streams its output to HBM.
+// k_binomial_starts, one thread per root: the root's coordinates from its cell's record, staged
+// through LDS so that the launch streams its output to HBM in contiguous pieces.
 #include <hip/hip_runtime.h>
 
 #include <climits>
