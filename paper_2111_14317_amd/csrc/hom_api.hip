@@ -521,7 +521,9 @@ int hom_create(int n, const int32_t *m, const int8_t *A, const double *w, int fl
                        reinterpret_cast<const double *>(b + o_EAd),
                        reinterpret_cast<const uint4 *>(b + o_CBb),
                        reinterpret_cast<const double *>(b + o_CBd),
-                       reinterpret_cast<const double *>(b + o_W)};
+                       reinterpret_cast<const double *>(b + o_W),
+                       std::all_of(D.W.begin(), D.W.end(),
+                                   [](double v) { return (double)(float)v == v; }) ? 1 : 0};
   }
   *out = h;
   return HOM_OK;

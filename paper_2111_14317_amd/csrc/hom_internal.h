@@ -48,6 +48,7 @@ struct DenseDev {
   const uint4 *CBb;      // [Md/32][2][64] bf16x8: exponent columns, bf16 engine B operand
   const double *CBd;     // [Md/16][4][2][64]: exponent columns, FP64 engine B operand
   const double *W;       // [Md] lifting
+  int w_f32;             // every lifting is exactly a float (the BF16x3 engine stages them so)
 };
 
 struct System {

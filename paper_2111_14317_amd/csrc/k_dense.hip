@@ -193,8 +193,11 @@ __device__ __forceinline__ void store_row_lean(OutT *__restrict__ G, double *__r
 // ------------------------------------------------------------------------------------------
 // BF16x3 engine
 // ------------------------------------------------------------------------------------------
-// LW: the liftings and the FP32 coefficients (16 bytes per monomial) are staged in LDS once per
-// block, when they fit kDenseLdsBytes; else read from global memory per term.
+// LW: the liftings and the FP32 coefficients are staged in LDS once per block, when they fit
+// kDenseLdsBytes; else read from global memory per term.  WF: every lifting is exactly a float
+// (integers below 2^24, as the method's liftings usually are; the handle records it), so they are
+// staged as float: 12 bytes per monomial instead of 16, 48 KiB at n = 32, m = 128, which lets
+// three blocks (three waves per SIMD) onto a CU instead of two.
 constexpr size_t kDenseLdsBytes = 64 * 1024;
 constexpr size_t kCuLdsBytes = 160 * 1024;  // LDS of one CU
 
@@ -202,10 +205,15 @@ constexpr size_t kCuLdsBytes = 160 * 1024;  // LDS of one CU
 #define HOM_BF16_WAVES 4  // waves per block (they share the block's staged tables)
 #endif
 #ifndef HOM_BF16_EU
-#define HOM_BF16_EU 2  // waves per SIMD the register budget is set for
+#define HOM_BF16_EU 3  // waves per SIMD the register budget is set for
 #endif
 constexpr int kBf16Block = 64 * HOM_BF16_WAVES;
-template <typename OutT, bool LW, int NCT>
+// byte offset of the staged coefficients, after the Md liftings (float or double; 8-byte aligned)
+template <bool WF>
+__host__ __device__ constexpr size_t bf16_stage_c_offset(int Md) {
+  return WF ? ((size_t)Md * 4 + 7) / 8 * 8 : (size_t)Md * 8;
+}
+template <typename OutT, bool LW, int NCT, bool WF>
 __global__ void __launch_bounds__(kBf16Block) __attribute__((amdgpu_waves_per_eu(HOM_BF16_EU)))
     k_dense_bf16(DenseDev D, const Cx<float> *__restrict__ Cf, int64_t p0, int64_t p1,
                  const double *__restrict__ z, const double *__restrict__ s, OutT *__restrict__ G,
@@ -214,15 +222,18 @@ __global__ void __launch_bounds__(kBf16Block) __attribute__((amdgpu_waves_per_eu
   __shared__ double sK[kCoefCount];  // the polynomial constants of exp and sin/cos (the store)
   stage_coefficients(sK);
   const double *Wt = D.W;
+  const float *Wf = nullptr;
   const Cx<float> *Ct = Cf;
   if constexpr (LW) {
-    double *sW = reinterpret_cast<double *>(smem);
-    Cx<float> *sC = reinterpret_cast<Cx<float> *>(sW + D.Md);
+    using WT = typename std::conditional<WF, float, double>::type;
+    WT *sW = reinterpret_cast<WT *>(smem);
+    Cx<float> *sC = reinterpret_cast<Cx<float> *>(smem + bf16_stage_c_offset<WF>(D.Md));
     for (int i = threadIdx.x; i < D.Md; i += blockDim.x) {
-      sW[i] = D.W[i];
+      sW[i] = (WT)D.W[i];
       sC[i] = Cf[i];
     }
-    Wt = sW;
+    if constexpr (WF) Wf = reinterpret_cast<const float *>(sW);
+    else Wt = reinterpret_cast<const double *>(sW);
     Ct = sC;
   }
   __syncthreads();
@@ -301,7 +312,7 @@ __global__ void __launch_bounds__(kBf16Block) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = t * 16 + row_f32(q, r);
-            const double w = Wt[i];
+            const double w = (LW && WF) ? (double)Wf[i] : Wt[i];
             const float e = dr[r] + (float)fma(w, sp, -Mk);
             const float mag = __builtin_amdgcn_exp2f(e * (float)kLog2e);
             // phase in turns from the exact digit sums: fract(d1/512 + d2/512^2) + d3/512^3
@@ -803,7 +814,9 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
   prof_begin(stream);
   unsigned long long *units = prof_units(stream);
   const dim3 grid(dense_grid(p1 - p0)), block(kDenseBlock);
-  const size_t lw = (size_t)S.Md * 16;
+  const bool wf = S.dense.w_f32 != 0;
+  const size_t lw = (wf ? bf16_stage_c_offset<true>(S.Md) : bf16_stage_c_offset<false>(S.Md)) +
+                    (size_t)S.Md * 8;
   if (engine == 1) {
     const int64_t tiles = (p1 - p0 + 15) / 16, need = (tiles + HOM_BF16_WAVES - 1) / HOM_BF16_WAVES;
     const dim3 bb(kBf16Block);
@@ -811,21 +824,19 @@ static void dense_launch(const System &S, int engine, const Cx<double> *Cd, cons
       const int64_t per = (int64_t)(kCuLdsBytes / lw) < 8 ? (int64_t)(kCuLdsBytes / lw) : 8;
       const int64_t cap = per * (int64_t)num_cus();
       const dim3 g2((unsigned)(need < cap ? (need > 0 ? need : 1) : cap));
-      if (S.dense.nct == 1)
-        hipLaunchKernelGGL((k_dense_bf16<OutT, true, 1>), g2, bb, lw, stream, S.dense, Cf, p0, p1,
-                           z, s, G, logscale, flags, units);
-      else
-        hipLaunchKernelGGL((k_dense_bf16<OutT, true, 2>), g2, bb, lw, stream, S.dense, Cf, p0, p1,
-                           z, s, G, logscale, flags, units);
+      auto kern = S.dense.nct == 1 ? (wf ? k_dense_bf16<OutT, true, 1, true> : k_dense_bf16<OutT, true, 1, false>)
+                                   : (wf ? k_dense_bf16<OutT, true, 2, true> : k_dense_bf16<OutT, true, 2, false>);
+      hipLaunchKernelGGL(kern, g2, bb, lw, stream, S.dense, Cf, p0, p1, z, s, G, logscale, flags,
+                         units);
     } else {
       const int64_t cap = (int64_t)num_cus() * 8;
       const dim3 g1((unsigned)(need < cap ? (need > 0 ? need : 1) : cap));
       if (S.dense.nct == 1)
-        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 1>), g1, bb, 0, stream, S.dense, Cf, p0, p1,
-                           z, s, G, logscale, flags, units);
+        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 1, false>), g1, bb, 0, stream, S.dense, Cf, p0,
+                           p1, z, s, G, logscale, flags, units);
       else
-        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 2>), g1, bb, 0, stream, S.dense, Cf, p0, p1,
-                           z, s, G, logscale, flags, units);
+        hipLaunchKernelGGL((k_dense_bf16<OutT, false, 2, false>), g1, bb, 0, stream, S.dense, Cf, p0,
+                           p1, z, s, G, logscale, flags, units);
     }
   } else if (S.union_support) {  // common support: the exponentials once per point
     const size_t lds = kUnionCoefBytes + (size_t)S.union_tiles * 4 * 64 * 16;

@@ -57,6 +57,22 @@ def test_dense_eval_c3_shape(hom, name, flags, tol):
         assert np.abs(L - Lo).max() <= 0.25
 
 
+def test_dense_bf16_rational_liftings(hom):
+    """The BF16x3 engine stages the liftings as float only when every one is exactly a float; with
+    liftings k + 1/3 (not floats) it reads the FP64 liftings instead and stays within its bound."""
+    import dataclasses
+    say("[dense eval bf16x3] liftings k + 1/3, P=200")
+    sys0, z, s = W.config_system("c3", P=200)
+    sys = dataclasses.replace(sys0, w=sys0.w + 1.0 / 3.0)
+    assert np.any(sys.w.astype(np.float32).astype(np.float64) != sys.w)
+    h = hom.System.from_workload(sys)
+    G, L = hom.eval(h, sys.c, z, s, flags=4)
+    Go, Lo, den = oracle.eval(sys, sys.c, z, s, with_den=True)
+    err = eval_err_fp32(_np(G), _np(L), Go, Lo, den)
+    say(f"  max scaled err {err.max():.3e}")
+    assert np.isfinite(_np(G)).all() and err.max() <= 1e-5
+
+
 @pytest.mark.parametrize("name,flags,tol", ENGINES)
 def test_dense_eval_ragged(hom, name, flags, tol):
     say(f"[dense eval ragged] {name} n=20 m_k in [30,70] P=37")
