@@ -148,6 +148,36 @@ def test_full_size_cell_properties(hom):
     assert len(np.unique(lat, axis=0)) == len(zn)
 
 
+@pytest.mark.parametrize("factors", [(1, 1, 540000), (1, 600, 1200)])
+def test_large_cells_sub_ranges(hom, factors):
+    """Cells of 540,000 roots (one invariant factor above one: each thread's later roots come from
+    fixed increments) and 720,000 roots (two factors: every digit computed): a sub-range call
+    returns bitwise the same roots as the matching slice of the whole cell; sampled roots satisfy
+    the system to within the rounding of z times the exponents; all roots are pairwise distinct."""
+    import torch
+    U = np.array([[1, 2, 0], [0, 1, 0], [3, 0, 1]])  # unimodular
+    V = np.array([[1, 0, 0], [1, 1, 0], [2, 5, 1]])
+    D = U @ np.diag(factors) @ V
+    det = int(np.prod(factors))
+    assert round(abs(np.linalg.det(D.astype(float)))) == det
+    beta = np.array([0.7 + 0.2j, -1.3 + 0.4j, 0.1 - 2.0j])
+    say(f"[binomial] n=3 cell with factors {factors}, {det} roots")
+    z, num = hom.binomial_starts(D, beta)
+    assert num[0] == det and len(z) == det
+    first, count = 12345, 200000
+    zs, _ = hom.binomial_starts(D, beta, first=[first], count=[count])
+    assert torch.equal(zs, z[first:first + count])
+    idx = np.random.default_rng(7).choice(det, 4096, replace=False)
+    samp = z[torch.as_tensor(idx, device=z.device)].cpu().numpy()
+    # exponents up to 2.7e6: rounding z to doubles alone moves D z by about eps sum_j |D_kj| |z_j|
+    scale = (np.abs(samp) @ np.abs(D).T.astype(np.float64)).max(1)
+    assert (_residual(D, beta, samp) <= 1e-12 + 16 * 2.0 ** -52 * scale).all()
+    zn = z.cpu().numpy()
+    L = int(factors[-1])
+    lat = np.mod(np.rint((zn.imag - zn[:1].imag) / (2 * np.pi) * L).astype(np.int64), L)
+    assert len(np.unique(lat, axis=0)) == det
+
+
 def test_plan_counts_and_errors(hom):
     """The GPU plan's root counts equal |det D| (numpy) and the oracle's; singular D, zero beta,
     a range outside a cell's roots and too few output rows are refused (HOM_EINVAL); a largest
