@@ -13,7 +13,8 @@
 // (the second run repeats the first one's operations and carries V modulo the L the first run
 // found), and z_base by an FP64 LU solve; it writes the cell's record.
 // k_binomial_starts, one thread per root: the root's coordinates from its cell's record, staged
-// through LDS so that the launch streams its output to HBM in contiguous pieces.
+// through LDS so that the launch streams its output to HBM in contiguous pieces; for few roots,
+// k_binomial_starts_coord, one thread per coordinate, with the same arithmetic.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -285,6 +286,70 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// The fractional part (times L) of coordinate i of root index q of a cell: the mixed-radix
+// digits of q over the cell's factors above one (first fastest; the last digit is what remains)
+// times the V columns, mod L.
+__device__ __forceinline__ int64_t root_num(int64_t q, int nlive, const int64_t *rs,
+                                            const int64_t *rc, int n, int i, int64_t L,
+                                            double inv_L) {
+  int64_t acc = 0;
+  for (int l = 0; l < nlive; ++l) {
+    int64_t j = q;
+    if (l + 1 < nlive) {
+      const int64_t sg = rs[l];
+      q = divmod62(q, sg, 1.0 / (double)sg, j);
+    }
+    int64_t t;  // j < sigma_l <= L and the column entry < L: the product is below 2^62
+    divmod62(j * rc[(int64_t)l * n + i], L, inv_L, t);
+    acc += t;
+    if (acc >= L) acc -= L;
+  }
+  return acc;
+}
+
+// Im z of a coordinate: its base value plus 2 pi num / L, reduced into [-pi, pi)
+__device__ __forceinline__ double root_im(double zi0, int64_t num, double inv_L) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double pi = 3.14159265358979323846264338327950;
+  double im = zi0 + two_pi * ((double)num * inv_L) + pi;
+  im -= two_pi * floor(im / two_pi);
+  im -= pi;
+  if (im >= pi) im -= two_pi;  // rounding at the top edge
+  return im;
+}
+
+// Few roots (many small cells): one thread per (root, coordinate), so that the launch has enough
+// threads; the same arithmetic as the kernel below, so the same results.
+__global__ void __launch_bounds__(256)
+    k_binomial_starts_coord(int n, int num_cells, const StartHdr *__restrict__ hdr,
+                            const int64_t *__restrict__ rec_all, int64_t rows,
+                            double *__restrict__ z) {
+  const int64_t total = rows * n;
+  const double inv_n = 1.0 / (double)n;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t ii;
+    const int64_t row = divmod62(g, n, inv_n, ii);
+    const int i = (int)ii;
+    int lo = 0, hi = num_cells - 1;  // last cell with row0 <= row
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hdr[mid].row0 <= row) lo = mid;
+      else hi = mid - 1;
+    }
+    const StartHdr h = hdr[lo];
+    const int64_t *d = rec_all + (int64_t)lo * start_record_words(n);
+    const int64_t L = d[0];
+    const int nlive = (int)d[1];
+    const int64_t *rs = d + 2 + 2 * n, *rc = rs + nlive;
+    const double inv_L = 1.0 / (double)L;
+    const int64_t num = root_num(h.first + (row - h.row0), nlive, rs, rc, n, i, L, inv_L);
+    reinterpret_cast<double2 *>(z)[g] =
+        double2{__longlong_as_double(d[2 + 2 * i]),
+                root_im(__longlong_as_double(d[3 + 2 * i]), num, inv_L)};
+  }
+}
+
 // One thread per root row, 64 rows per block (one wave) per tile, grid-stride over tiles: the
 // cell by binary search over the rows' starts (skipped while the row stays in the previous row's
 // cell), the root index's mixed-radix digits over the cell's invariant factors above one (first
@@ -302,8 +367,6 @@ __global__ void __launch_bounds__(kStartTile)
   const int t = threadIdx.x;
   const int64_t tiles = (rows + kStartTile - 1) / kStartTile;
   const int64_t stride = (int64_t)gridDim.x * kStartTile;  // rows between a thread's rows
-  const double two_pi = 6.283185307179586476925286766559;
-  const double pi = 3.14159265358979323846264338327950;
   int cur = -1;         // cell of this thread's previous row
   int64_t prev_q = -1;  // its root index
   int64_t num[KN], inc[KN];
@@ -354,38 +417,16 @@ __global__ void __launch_bounds__(kStartTile)
         }
       } else {  // several factors: every digit, every product
 #pragma unroll
-        for (int i = 0; i < KN; ++i) {
-          if (i < n) {
-            int64_t qq = q, acc = 0;
-            for (int l = 0; l < nlive; ++l) {
-              int64_t j = qq;
-              if (l + 1 < nlive) {
-                const int64_t sg = rs[l];
-                qq = divmod62(qq, sg, 1.0 / (double)sg, j);
-              }
-              int64_t tq;  // j < sigma_l <= L and the column entry < L: below 2^62
-              divmod62(j * rc[(int64_t)l * n + i], L, inv_L, tq);
-              acc += tq;
-              if (acc >= L) acc -= L;
-            }
-            num[i] = acc;
-          }
-        }
+        for (int i = 0; i < KN; ++i)
+          if (i < n) num[i] = root_num(q, nlive, rs, rc, n, i, L, inv_L);
       }
       cur = lo;
       prev_q = q;
 #pragma unroll
-      for (int i = 0; i < KN; ++i) {
-        if (i < n) {
-          const double zr = __longlong_as_double(d[2 + 2 * i]);
-          const double zi0 = __longlong_as_double(d[3 + 2 * i]);
-          double im = zi0 + two_pi * ((double)num[i] * inv_L) + pi;
-          im -= two_pi * floor(im / two_pi);
-          im -= pi;
-          if (im >= pi) im -= two_pi;  // rounding at the top edge
-          stage[t * n + i] = double2{zr, im};
-        }
-      }
+      for (int i = 0; i < KN; ++i)
+        if (i < n)
+          stage[t * n + i] = double2{__longlong_as_double(d[2 + 2 * i]),
+                                     root_im(__longlong_as_double(d[3 + 2 * i]), num[i], inv_L)};
     }
     __syncthreads();
     const int64_t r0 = tile * kStartTile;
@@ -430,6 +471,16 @@ hipError_t launch_start_plan(int n, int64_t num_cells, const int32_t *D, const d
 hipError_t launch_binomial_starts(int n, int num_cells, const StartHdr *hdr, const int64_t *rec,
                                   int64_t rows, double *z, hipStream_t stream) {
   prof_begin(stream);
+  if (rows * n <= ((int64_t)1 << 20)) {  // few roots: a thread per coordinate fills the GPU better
+    int64_t blocks = (rows * n + 255) / 256;
+    const int64_t cap = (int64_t)num_cus() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_binomial_starts_coord, dim3((unsigned)blocks), dim3(256), 0, stream, n,
+                       num_cells, hdr, rec, rows, z);
+    prof_end(stream, "k_binomial_starts");
+    return hipGetLastError();
+  }
   const int64_t tiles = (rows + kStartTile - 1) / kStartTile;
   int64_t blocks = tiles;
   const int64_t cap = (int64_t)num_cus() * 16;
