@@ -343,8 +343,8 @@ def run_union(hom, torch, P, reps=3):
 
 def run_starts(hom, torch, reps=3):
     """Start points of the n = 10 tracking workload's planted cell: all |det D| = 3,881,632 roots
-    of its binomial system (host Smith form, then one GPU launch writing 16 bytes per root
-    coordinate, judged against HBM)."""
+    of its binomial system (Smith form and base root planned on the GPU, then one launch writing
+    16 bytes per root coordinate, judged against HBM); and 1024 small random cells in one call."""
     import numpy as np
     import workloads as W
     csys, cell, _ = W.planted_config("c2", P=4)
