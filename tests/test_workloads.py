@@ -71,6 +71,16 @@ def test_configs_shapes():
     sys, _, _ = W.config_system("c3", P=16)
     frac0 = (sys.A == 0).mean()
     assert 0.25 < frac0 < 0.35 and np.abs(sys.A).max() == 4
+    # the sizes of the paper's timing systems: n = 14 with 184 monomials, n = 24 with 324, split
+    # as evenly as possible over the equations, 0/1 exponents with about 30% ones, distinct rows
+    for cfg, (n, M) in {"ps14": (14, 184), "ps24": (24, 324)}.items():
+        sys, z, s = W.config_system(cfg, P=1000)
+        assert sys.n == n and int(sys.m.sum()) == M and sys.m.max() - sys.m.min() <= 1
+        assert set(np.unique(sys.A)) <= {0, 1} and 0.25 < sys.A.mean() < 0.35
+        assert z.shape == (1000, n)
+        for k in range(n):
+            rows = {tuple(r) for r in sys.A[sys.equation(k)]}
+            assert len(rows) == sys.m[k]
 
 
 def test_seeded_reproducible():
